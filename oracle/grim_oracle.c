@@ -1,0 +1,1232 @@
+/*
+ * Plain FP64 CPU oracle of the grim method (Chandra, Foucart & Gammie,
+ * "grim: A Flexible, Conservative Scheme for Relativistic Fluid Theories").
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only code that may load this
+ * library.  It shares no source with the GPU library.
+ *
+ * The code is deliberately plain: one zone at a time, no blocking, no
+ * fusion, geometry recomputed wherever it is needed.  Each routine names the
+ * passage of the paper it follows.  Where the paper is silent, garbled or
+ * inconsistent, the reading taken is stated beside the code and listed in
+ * the design notes of the repository.
+ */
+#include "grim_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7, QQ = 8, DP = 9 };
+#define NVMAX 10
+
+/* ------------------------------------------------------------------------ */
+/* grid layout                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int N[3];   /* ghosted extents */
+    int g[3];   /* ghost offsets (0 for inactive directions) */
+    int n[3];   /* interior extents */
+    size_t cells;
+} olay_t;
+
+static olay_t o_layout(const ocfg_t* c)
+{
+    olay_t L;
+    L.n[0] = c->n1;
+    L.n[1] = c->ndim >= 2 ? c->n2 : 1;
+    L.n[2] = c->ndim >= 3 ? c->n3 : 1;
+    for (int d = 0; d < 3; ++d) {
+        L.g[d] = (d < c->ndim) ? c->ng : 0;
+        L.N[d] = L.n[d] + 2 * L.g[d];
+    }
+    L.cells = (size_t)L.N[0] * L.N[1] * L.N[2];
+    return L;
+}
+
+static size_t o_cell(const olay_t* L, int i, int j, int k)
+{
+    return ((size_t)k * L->N[1] + j) * L->N[0] + i;
+}
+
+static size_t o_zones(const olay_t* L)
+{
+    return (size_t)L->n[0] * L->n[1] * L->n[2];
+}
+
+static void o_zone_X(const ocfg_t* c, const olay_t* L, int i, int j, int k, double X[4])
+{
+    X[0] = 0.0;
+    X[1] = c->x1s + (i - L->g[0] + 0.5) * c->dx1;
+    X[2] = c->x2s + (j - L->g[1] + 0.5) * c->dx2;
+    X[3] = c->x3s + (k - L->g[2] + 0.5) * c->dx3;
+}
+
+static double o_dx(const ocfg_t* c, int d)
+{
+    return d == 0 ? c->dx1 : (d == 1 ? c->dx2 : c->dx3);
+}
+
+/* ------------------------------------------------------------------------ */
+/* geometry (Sec. 2.1, eq. theta_transform and the matrix L)                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double gcov[4][4], gcon[4][4], gdet, alpha;
+} ogeom_t;
+
+/* Inverse and determinant of a 4x4 matrix by Gauss-Jordan elimination with
+ * partial pivoting. */
+static double o_inv4(const double A[4][4], double Ai[4][4])
+{
+    double M[4][8];
+    double det = 1.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) M[i][j] = (j < 4) ? A[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+        if (p != k) {
+            for (int j = 0; j < 8; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+            det = -det;
+        }
+        double piv = M[k][k];
+        det *= piv;
+        for (int j = 0; j < 8; ++j) M[k][j] /= piv;
+        for (int i = 0; i < 4; ++i) {
+            if (i == k) continue;
+            double f = M[i][k];
+            for (int j = 0; j < 8; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) Ai[i][j] = M[i][j + 4];
+    return det;
+}
+
+/* Covariant metric at coordinate point X.
+ * Minkowski: diag(-1, 1, 1, 1) in Cartesian X^i.
+ * Modified Kerr-Schild: Kerr in Kerr-Schild (t, r, theta, phi), mapped with
+ * r = exp(X1), theta = pi X2 + (1-h)/2 sin(2 pi X2), phi = X3 (Sec. 2.1),
+ * g_{mu nu}(X) = g_{ab}(x) L^a_mu L^b_nu with L = diag(1, r, dtheta/dX2, 1).
+ * Reading: theta is kept at least 1e-12 away from the poles so that the
+ * inverse metric stays finite on the polar faces (sqrt(-g) ~ 1e-12 there). */
+static void o_metric_cov(const ocfg_t* c, const double X[4], double g[4][4])
+{
+    memset(g, 0, sizeof(double) * 16);
+    if (c->metric == 0) {
+        g[0][0] = -1.0; g[1][1] = 1.0; g[2][2] = 1.0; g[3][3] = 1.0;
+        return;
+    }
+    const double a = c->spin, h = c->hslope;
+    double r = exp(X[1]);
+    double th = M_PI * X[2] + 0.5 * (1.0 - h) * sin(2.0 * M_PI * X[2]);
+    if (th < 1e-12) th = 1e-12;
+    if (th > M_PI - 1e-12) th = M_PI - 1e-12;
+    double dr_dX1 = r;
+    double dth_dX2 = M_PI * (1.0 + (1.0 - h) * cos(2.0 * M_PI * X[2]));
+    double cth = cos(th), sth = sin(th), s2 = sth * sth;
+    double Sig = r * r + a * a * cth * cth;
+    double ks[4][4];
+    memset(ks, 0, sizeof(ks));
+    ks[0][0] = -(1.0 - 2.0 * r / Sig);
+    ks[0][1] = ks[1][0] = 2.0 * r / Sig;
+    ks[0][3] = ks[3][0] = -2.0 * a * r * s2 / Sig;
+    ks[1][1] = 1.0 + 2.0 * r / Sig;
+    ks[1][3] = ks[3][1] = -a * s2 * (1.0 + 2.0 * r / Sig);
+    ks[2][2] = Sig;
+    ks[3][3] = s2 * (Sig + a * a * s2 * (1.0 + 2.0 * r / Sig));
+    double Ld[4] = {1.0, dr_dX1, dth_dX2, 1.0};
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) g[m][n] = ks[m][n] * Ld[m] * Ld[n];
+}
+
+static void o_geom(const ocfg_t* c, const double X[4], ogeom_t* G)
+{
+    o_metric_cov(c, X, G->gcov);
+    double det = o_inv4(G->gcov, G->gcon);
+    G->gdet = sqrt(fabs(det));
+    G->alpha = 1.0 / sqrt(-G->gcon[0][0]);
+}
+
+/* Christoffel symbols conn[l][a][b] = Gamma^l_{ab}
+ * = 1/2 g^{lk} (d_a g_kb + d_b g_ka - d_k g_ab), with the metric derivatives
+ * taken by central differences of step 1e-5 in X. */
+static void o_conn(const ocfg_t* c, const double X[4], double conn[4][4][4])
+{
+    const double del = 1e-5;
+    double dg[4][4][4]; /* dg[k][a][b] = d_k g_ab */
+    for (int k = 0; k < 4; ++k) {
+        double Xp[4], Xm[4], gp[4][4], gm[4][4];
+        for (int m = 0; m < 4; ++m) { Xp[m] = X[m]; Xm[m] = X[m]; }
+        Xp[k] += del;
+        Xm[k] -= del;
+        o_metric_cov(c, Xp, gp);
+        o_metric_cov(c, Xm, gm);
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) dg[k][a][b] = (gp[a][b] - gm[a][b]) / (2.0 * del);
+    }
+    ogeom_t G;
+    o_geom(c, X, &G);
+    for (int l = 0; l < 4; ++l)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 4; ++k)
+                    s += G.gcon[l][k] * (dg[a][k][b] + dg[b][k][a] - dg[k][a][b]);
+                conn[l][a][b] = 0.5 * s;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* derived quantities of a primitive state (Sec. 4)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double ucon[4], ucov[4], bcon[4], bcov[4];
+    double bhcon[4], bhcov[4];
+    double bsq, pg, gamL;
+} ostate_t;
+
+/* The velocity primitives are read as the normal-observer four-velocity
+ * utilde^i (the paper inherits the harm convention); they equal u^i in
+ * Minkowski.  b^t = B^i u_i, b^i = (B^i + b^t u^i)/u^t (Sec. 4), P = (gamma-1)u.
+ * The unit vector bhat = b / sqrt(b^2) is set to zero when b^2 < 1e-30. */
+static void o_state(const ocfg_t* c, const double* P, const ogeom_t* G, ostate_t* S)
+{
+    double qsq = 0.0;
+    for (int i = 1; i < 4; ++i)
+        for (int j = 1; j < 4; ++j) qsq += G->gcov[i][j] * P[U1 + i - 1] * P[U1 + j - 1];
+    S->gamL = sqrt(1.0 + qsq);
+    S->ucon[0] = S->gamL / G->alpha;
+    for (int i = 1; i < 4; ++i)
+        S->ucon[i] = P[U1 + i - 1] - S->gamL * G->alpha * G->gcon[0][i];
+    for (int m = 0; m < 4; ++m) {
+        S->ucov[m] = 0.0;
+        for (int n = 0; n < 4; ++n) S->ucov[m] += G->gcov[m][n] * S->ucon[n];
+    }
+    S->bcon[0] = 0.0;
+    for (int i = 1; i < 4; ++i) S->bcon[0] += P[B1 + i - 1] * S->ucov[i];
+    for (int i = 1; i < 4; ++i)
+        S->bcon[i] = (P[B1 + i - 1] + S->bcon[0] * S->ucon[i]) / S->ucon[0];
+    for (int m = 0; m < 4; ++m) {
+        S->bcov[m] = 0.0;
+        for (int n = 0; n < 4; ++n) S->bcov[m] += G->gcov[m][n] * S->bcon[n];
+    }
+    S->bsq = 0.0;
+    for (int m = 0; m < 4; ++m) S->bsq += S->bcon[m] * S->bcov[m];
+    S->pg = (c->gam - 1.0) * P[UU];
+    if (S->bsq > 1e-30) {
+        double bm = sqrt(S->bsq);
+        for (int m = 0; m < 4; ++m) { S->bhcon[m] = S->bcon[m] / bm; S->bhcov[m] = S->bcov[m] / bm; }
+    } else {
+        for (int m = 0; m < 4; ++m) { S->bhcon[m] = 0.0; S->bhcov[m] = 0.0; }
+    }
+}
+
+/* Mixed stress tensor T^mu_nu (eq. fullSEtens with q^mu = q bhat^mu and
+ * Pi^{mu nu} = -DeltaP (bhat^mu bhat^nu - h^{mu nu}/3)).  Expanding
+ * h = g + u u turns the first two terms into
+ * (rho + u + P + b^2) u^mu u_nu + (P + b^2/2) delta^mu_nu. */
+static void o_tmunu(const ocfg_t* c, const double* P, const ostate_t* S, double T[4][4])
+{
+    double w = P[RHO] + P[UU] + S->pg + S->bsq;
+    double pt = S->pg + 0.5 * S->bsq;
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) {
+            double t = w * S->ucon[m] * S->ucov[n] + (m == n ? pt : 0.0) - S->bcon[m] * S->bcov[n];
+            if (c->nvar == 10) {
+                double hmn = (m == n ? 1.0 : 0.0) + S->ucon[m] * S->ucov[n];
+                t += P[QQ] * (S->bhcon[m] * S->ucov[n] + S->ucon[m] * S->bhcov[n]);
+                t -= P[DP] * (S->bhcon[m] * S->bhcov[n] - hmn / 3.0);
+            }
+            T[m][n] = t;
+        }
+}
+
+/* Rescaled dissipative variables, eqs. (q) and (dP):
+ * qtilde = q sqrt(tau_R / (chi rho Theta^2)), DPtilde = DP sqrt(tau_R / (nu rho Theta)),
+ * with Theta = P/rho. */
+static void o_rescaled(const ocfg_t* c, const double* P, const ostate_t* S, double* qt, double* dpt)
+{
+    double theta = S->pg / P[RHO];
+    *qt = P[QQ] * sqrt(c->tau_R / (c->chi * P[RHO] * theta * theta));
+    *dpt = P[DP] * sqrt(c->tau_R / (c->nu * P[RHO] * theta));
+}
+
+/* dir = 0: conserved vector U; dir = d in 1..3: flux F^d.
+ * Rows: sqrt(-g) (rho u^dir, T^dir_nu (nu = 0..3), induction, qtilde u^dir,
+ * DPtilde u^dir) (eqs. divN_explicit, divT_explicit, induction_eqn,
+ * q_evol_eqn_rescaled, dP_evol_eqn_rescaled).
+ * Reading: the induction flux is F^j_{B^i} = sqrt(-g)(b^i u^j - b^j u^i).
+ * The paper prints the opposite sign, which would advect B against the flow
+ * (and turns Alfven waves unstable); the sign here is the one that follows
+ * from the divergence of the dual field tensor with B^i = *F^{it}.  For
+ * dir = 0 the row reduces to sqrt(-g) B^i. */
+static void o_flux_from_state(const ocfg_t* c, const double* P, const ogeom_t* G, const ostate_t* S,
+                              int dir, double* out)
+{
+    double T[4][4];
+    o_tmunu(c, P, S, T);
+    out[RHO] = G->gdet * P[RHO] * S->ucon[dir];
+    for (int n = 0; n < 4; ++n) out[UU + n] = G->gdet * T[dir][n];
+    for (int i = 1; i < 4; ++i)
+        out[B1 + i - 1] = G->gdet * (S->bcon[i] * S->ucon[dir] - S->bcon[dir] * S->ucon[i]);
+    if (c->nvar == 10) {
+        double qt, dpt;
+        o_rescaled(c, P, S, &qt, &dpt);
+        out[QQ] = G->gdet * qt * S->ucon[dir];
+        out[DP] = G->gdet * dpt * S->ucon[dir];
+    }
+}
+
+/* Upper bound on the fluid-frame wave speed (Sec. 4.1, eq. modcs):
+ * v_max^2 = ct^2 + vA^2 - ct^2 vA^2, vA^2 = b^2/(rho + gamma u + b^2),
+ * cs^2 = gamma (gamma-1) u/(rho + gamma u),
+ * ct^2 = (cs^2 + vq^2 + sqrt(cs^4 + vq^4))/2 + vdP^2,
+ * vq^2 = (gamma-1) chi/tau_R, vdP^2 = 4 nu/(3 tau_R).  Ideal MHD: ct = cs. */
+static double o_vmax2_state(const ocfg_t* c, const double* P, const ostate_t* S)
+{
+    double g = c->gam;
+    double cs2 = g * (g - 1.0) * P[UU] / (P[RHO] + g * P[UU]);
+    double va2 = S->bsq / (P[RHO] + g * P[UU] + S->bsq);
+    double ct2 = cs2;
+    if (c->nvar == 10) {
+        double vq2 = (g - 1.0) * c->chi / c->tau_R;
+        double vd2 = 4.0 * c->nu / (3.0 * c->tau_R);
+        ct2 = 0.5 * (cs2 + vq2 + sqrt(cs2 * cs2 + vq2 * vq2)) + vd2;
+    }
+    return ct2 + va2 - ct2 * va2;
+}
+
+/* Grid-frame speeds of waves moving at +-v_max in the fluid frame along
+ * direction dir (Sec. 4.1).  A wave covector k = (-lambda, e_dir) at fluid-frame
+ * phase speed v satisfies (k.u)^2 = v^2 (k.k + (k.u)^2), a quadratic in
+ * lambda. */
+static void o_speeds_state(const ocfg_t* c, const double* P, const ogeom_t* G, const ostate_t* S,
+                           int dir, double* lp, double* lm)
+{
+    double v2 = o_vmax2_state(c, P, S);
+    double u0 = S->ucon[0], ud = S->ucon[dir];
+    double A = (1.0 - v2) * u0 * u0 - v2 * G->gcon[0][0];
+    double B = -2.0 * ((1.0 - v2) * u0 * ud - v2 * G->gcon[0][dir]);
+    double C = (1.0 - v2) * ud * ud - v2 * G->gcon[dir][dir];
+    double disc = B * B - 4.0 * A * C;
+    if (disc < 0.0) disc = 0.0;
+    double sq = sqrt(disc);
+    double x1 = (-B + sq) / (2.0 * A), x2 = (-B - sq) / (2.0 * A);
+    *lp = x1 > x2 ? x1 : x2;
+    *lm = x1 > x2 ? x2 : x1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reconstruction and Riemann solver (Sec. 2.4)                              */
+/* ------------------------------------------------------------------------ */
+
+/* generalized minmod slope minmod(theta a, (a+b)/2, theta b) */
+static double o_gmm(double a, double b, double th)
+{
+    double x = th * a, y = 0.5 * (a + b), z = th * b;
+    if (x > 0.0 && y > 0.0 && z > 0.0) return fmin(x, fmin(y, z));
+    if (x < 0.0 && y < 0.0 && z < 0.0) return fmax(x, fmax(y, z));
+    return 0.0;
+}
+
+static size_t o_stride(const olay_t* L, int d)
+{
+    return d == 0 ? 1 : (d == 1 ? (size_t)L->N[0] : (size_t)L->N[0] * L->N[1]);
+}
+
+/* LLF flux through the face on the low side of cell (i,j,k) in direction d
+ * (Sec. 2.4.1 reconstruction, Sec. 2.4.2 LLF). */
+static void o_face_flux(const ocfg_t* c, const olay_t* L, const double* Pg, int d, int i, int j, int k,
+                        double* F)
+{
+    const int nv = c->nvar;
+    size_t st = o_stride(L, d);
+    size_t m = o_cell(L, i, j, k);
+    double PL[NVMAX], PR[NVMAX];
+    for (int v = 0; v < nv; ++v) {
+        const double* a = Pg + (size_t)v * L->cells;
+        double pm2 = a[m - 2 * st], pm1 = a[m - st], p0 = a[m], pp1 = a[m + st];
+        double sl = o_gmm(pm1 - pm2, p0 - pm1, c->theta_plm);
+        double sr = o_gmm(p0 - pm1, pp1 - p0, c->theta_plm);
+        PL[v] = pm1 + 0.5 * sl;
+        PR[v] = p0 - 0.5 * sr;
+    }
+    double X[4];
+    o_zone_X(c, L, i, j, k, X);
+    X[d + 1] -= 0.5 * o_dx(c, d);
+    ogeom_t G;
+    o_geom(c, X, &G);
+    ostate_t SL, SR;
+    o_state(c, PL, &G, &SL);
+    o_state(c, PR, &G, &SR);
+    double UL[NVMAX], UR[NVMAX], FL[NVMAX], FR[NVMAX];
+    o_flux_from_state(c, PL, &G, &SL, 0, UL);
+    o_flux_from_state(c, PR, &G, &SR, 0, UR);
+    o_flux_from_state(c, PL, &G, &SL, d + 1, FL);
+    o_flux_from_state(c, PR, &G, &SR, d + 1, FR);
+    double lpL, lmL, lpR, lmR;
+    o_speeds_state(c, PL, &G, &SL, d + 1, &lpL, &lmL);
+    o_speeds_state(c, PR, &G, &SR, d + 1, &lpR, &lmR);
+    double cmax = fmax(fmax(fabs(lpL), fabs(lmL)), fmax(fabs(lpR), fabs(lmR)));
+    for (int v = 0; v < nv; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * cmax * (UR[v] - UL[v]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* boundary conditions                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Ghost fill, direction by direction (X1 on interior rows, then X2 on all X1
+ * cells, then X3 on everything) so that edges and corners are filled.
+ * periodic: wrap; outflow: copy the nearest interior zone; polar reflection:
+ * mirror across the axis with utilde^2 and B^2 negated. */
+static void o_fill_ghosts(const ocfg_t* c, const olay_t* L, double* Pg)
+{
+    const int bcs[3] = {c->bc1, c->bc2, c->bc3};
+    for (int d = 0; d < c->ndim; ++d) {
+        int g = L->g[d], n = L->n[d];
+        int lo[3], hi[3];
+        for (int e = 0; e < 3; ++e) {
+            if (e < d) { lo[e] = 0; hi[e] = L->N[e]; }
+            else { lo[e] = L->g[e]; hi[e] = L->g[e] + L->n[e]; }
+        }
+        for (int v = 0; v < c->nvar; ++v) {
+            double* a = Pg + (size_t)v * L->cells;
+            double sgn = 1.0;
+            if (bcs[d] == 2 && d == 1 && (v == U2 || v == B2)) sgn = -1.0;
+            for (int k = (d == 2 ? 0 : lo[2]); k < (d == 2 ? L->N[2] : hi[2]); ++k)
+                for (int j = (d == 1 ? 0 : lo[1]); j < (d == 1 ? L->N[1] : hi[1]); ++j)
+                    for (int i = (d == 0 ? 0 : lo[0]); i < (d == 0 ? L->N[0] : hi[0]); ++i) {
+                        int idx[3] = {i, j, k};
+                        int p = idx[d];
+                        if (p >= g && p < g + n) continue;
+                        int src;
+                        double s = 1.0;
+                        if (bcs[d] == 0) {
+                            src = p < g ? p + n : p - n;
+                        } else if (bcs[d] == 1) {
+                            src = p < g ? g : g + n - 1;
+                        } else {
+                            src = p < g ? 2 * g - 1 - p : 2 * (g + n) - 1 - p;
+                            s = sgn;
+                        }
+                        int sidx[3] = {i, j, k};
+                        sidx[d] = src;
+                        a[o_cell(L, i, j, k)] = s * a[o_cell(L, sidx[0], sidx[1], sidx[2])];
+                    }
+        }
+    }
+}
+
+static void o_to_ghosted(const ocfg_t* c, const olay_t* L, const double* Pint, double* Pg)
+{
+    size_t nz = o_zones(L);
+    for (int v = 0; v < c->nvar; ++v)
+        for (int k = 0; k < L->n[2]; ++k)
+            for (int j = 0; j < L->n[1]; ++j)
+                for (int i = 0; i < L->n[0]; ++i)
+                    Pg[(size_t)v * L->cells + o_cell(L, i + L->g[0], j + L->g[1], k + L->g[2])] =
+                        Pint[(size_t)v * nz + ((size_t)k * L->n[1] + j) * L->n[0] + i];
+    o_fill_ghosts(c, L, Pg);
+}
+
+static void o_get_cell(const ocfg_t* c, const olay_t* L, const double* Pg, size_t m, double* P)
+{
+    for (int v = 0; v < c->nvar; ++v) P[v] = Pg[(size_t)v * L->cells + m];
+}
+
+/* ------------------------------------------------------------------------ */
+/* explicit stage: fluxes, flux-CT, divergence, explicit sources             */
+/* ------------------------------------------------------------------------ */
+
+/* Zone-centred quantities for the EMHD sources that depend only on P^E:
+ * the spatial-derivative and connection parts of the q, DeltaP relaxation
+ * targets (eqs. q0def, dP0def) and of div u. */
+typedef struct {
+    double sq_sp;   /* bhat^i d_i Theta + Theta (bhat^mu u^i d_i u_mu - bhat^mu Gamma^l_{n mu} u^n u_l) */
+    double sdiv_sp; /* d_i u^i + Gamma^mu_{mu l} u^l                                                   */
+    double sdp_sp;  /* bhat^i bhat^n d_i u_n - bhat^mu bhat^n Gamma^l_{mu n} u_l                         */
+} oemhd_sp_t;
+
+/* For every interior zone: divF (eq. fvm_formulation), the explicit
+ * geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E (eq. divT_explicit),
+ * and for EMHD the P^E-only parts of the relaxation sources.
+ * Pg must be ghost-filled.  divF, srcE: [nvar][zones]; sp: [zones]. */
+static void o_explicit_stage(const ocfg_t* c, const olay_t* L, const double* Pg, double* divF,
+                             double* srcE, oemhd_sp_t* sp)
+{
+    const int nv = c->nvar;
+    const int nd = c->ndim;
+    double* Fd[3] = {NULL, NULL, NULL};
+    for (int d = 0; d < nd; ++d) Fd[d] = (double*)calloc((size_t)nv * L->cells, sizeof(double));
+
+    /* face fluxes: along d the faces of every interior cell; across the other
+     * active directions one extra row on each side (needed by flux-CT). */
+    for (int d = 0; d < nd; ++d) {
+        int lo[3], hi[3];
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) { lo[e] = L->g[e]; hi[e] = L->g[e] + L->n[e] + 1; }
+            else if (e < nd) { lo[e] = L->g[e] - 1; hi[e] = L->g[e] + L->n[e] + 1; }
+            else { lo[e] = 0; hi[e] = 1; }
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = lo[2]; k < hi[2]; ++k)
+            for (int j = lo[1]; j < hi[1]; ++j)
+                for (int i = lo[0]; i < hi[0]; ++i) {
+                    double F[NVMAX];
+                    o_face_flux(c, L, Pg, d, i, j, k, F);
+                    size_t m = o_cell(L, i, j, k);
+                    for (int v = 0; v < nv; ++v) Fd[d][(size_t)v * L->cells + m] = F[v];
+                }
+    }
+
+    /* The flux of B^d through faces normal to d is zero in the continuum;
+     * it is set to exactly zero (flux-CT does this in 2D and 3D). */
+    for (int d = 0; d < nd; ++d)
+        for (size_t m = 0; m < L->cells; ++m) Fd[d][(size_t)(B1 + d) * L->cells + m] = 0.0;
+
+    /* flux-CT (Sec. 4.2): average face EMFs to edges, edges back to faces. */
+    if (nd >= 2) {
+        size_t C = L->cells;
+        double* E1 = (double*)calloc(C, sizeof(double));
+        double* E2 = (double*)calloc(C, sizeof(double));
+        double* E3 = (double*)calloc(C, sizeof(double));
+        const int g1 = L->g[0], g2 = L->g[1], g3 = L->g[2];
+        const int n1 = L->n[0], n2 = L->n[1], n3 = L->n[2];
+        const size_t s1 = 1, s2 = L->N[0], s3 = (size_t)L->N[0] * L->N[1];
+        double* F1B2 = Fd[0] + (size_t)B2 * C;
+        double* F1B3 = Fd[0] + (size_t)B3 * C;
+        double* F2B1 = Fd[1] + (size_t)B1 * C;
+        double* F2B3 = Fd[1] + (size_t)B3 * C;
+        double* F3B1 = nd >= 3 ? Fd[2] + (size_t)B1 * C : NULL;
+        double* F3B2 = nd >= 3 ? Fd[2] + (size_t)B2 * C : NULL;
+        /* E3 on X3-edges at (i-1/2, j-1/2, k) */
+        for (int k = g3; k < g3 + n3; ++k)
+            for (int j = g2; j <= g2 + n2; ++j)
+                for (int i = g1; i <= g1 + n1; ++i) {
+                    size_t m = o_cell(L, i, j, k);
+                    E3[m] = 0.25 * (F1B2[m] + F1B2[m - s2] - F2B1[m] - F2B1[m - s1]);
+                }
+        if (nd >= 3) {
+            /* E1 on X1-edges at (i, j-1/2, k-1/2) */
+            for (int k = g3; k <= g3 + n3; ++k)
+                for (int j = g2; j <= g2 + n2; ++j)
+                    for (int i = g1; i < g1 + n1; ++i) {
+                        size_t m = o_cell(L, i, j, k);
+                        E1[m] = 0.25 * (F2B3[m] + F2B3[m - s3] - F3B2[m] - F3B2[m - s2]);
+                    }
+            /* E2 on X2-edges at (i-1/2, j, k-1/2) */
+            for (int k = g3; k <= g3 + n3; ++k)
+                for (int j = g2; j < g2 + n2; ++j)
+                    for (int i = g1; i <= g1 + n1; ++i) {
+                        size_t m = o_cell(L, i, j, k);
+                        E2[m] = 0.25 * (F3B1[m] + F3B1[m - s1] - F1B3[m] - F1B3[m - s3]);
+                    }
+        }
+        /* X1 faces */
+        for (int k = g3; k < g3 + n3; ++k)
+            for (int j = g2; j < g2 + n2; ++j)
+                for (int i = g1; i <= g1 + n1; ++i) {
+                    size_t m = o_cell(L, i, j, k);
+                    F1B2[m] = 0.5 * (E3[m] + E3[m + s2]);
+                    if (nd >= 3) F1B3[m] = -0.5 * (E2[m] + E2[m + s3]);
+                }
+        /* X2 faces */
+        for (int k = g3; k < g3 + n3; ++k)
+            for (int j = g2; j <= g2 + n2; ++j)
+                for (int i = g1; i < g1 + n1; ++i) {
+                    size_t m = o_cell(L, i, j, k);
+                    F2B1[m] = -0.5 * (E3[m] + E3[m + s1]);
+                    if (nd >= 3) F2B3[m] = 0.5 * (E1[m] + E1[m + s3]);
+                }
+        /* X3 faces */
+        if (nd >= 3)
+            for (int k = g3; k <= g3 + n3; ++k)
+                for (int j = g2; j < g2 + n2; ++j)
+                    for (int i = g1; i < g1 + n1; ++i) {
+                        size_t m = o_cell(L, i, j, k);
+                        F3B1[m] = 0.5 * (E2[m] + E2[m + s1]);
+                        F3B2[m] = -0.5 * (E1[m] + E1[m + s2]);
+                    }
+        free(E1);
+        free(E2);
+        free(E3);
+    }
+
+    /* divergence of the fluxes, explicit sources, EMHD spatial parts */
+    const size_t nz = o_zones(L);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int kk = 0; kk < L->n[2]; ++kk)
+        for (int jj = 0; jj < L->n[1]; ++jj)
+            for (int ii = 0; ii < L->n[0]; ++ii) {
+                int i = ii + L->g[0], j = jj + L->g[1], k = kk + L->g[2];
+                size_t z = ((size_t)kk * L->n[1] + jj) * L->n[0] + ii;
+                size_t m = o_cell(L, i, j, k);
+                for (int v = 0; v < nv; ++v) {
+                    double s = 0.0;
+                    for (int d = 0; d < nd; ++d) {
+                        size_t st = o_stride(L, d);
+                        s += (Fd[d][(size_t)v * L->cells + m + st] - Fd[d][(size_t)v * L->cells + m]) / o_dx(c, d);
+                    }
+                    divF[(size_t)v * nz + z] = s;
+                }
+                double X[4], P[NVMAX], conn[4][4][4], T[4][4];
+                o_zone_X(c, L, i, j, k, X);
+                ogeom_t G;
+                o_geom(c, X, &G);
+                o_conn(c, X, conn);
+                o_get_cell(c, L, Pg, m, P);
+                ostate_t S;
+                o_state(c, P, &G, &S);
+                o_tmunu(c, P, &S, T);
+                for (int v = 0; v < nv; ++v) srcE[(size_t)v * nz + z] = 0.0;
+                for (int n = 0; n < 4; ++n) {
+                    double s = 0.0;
+                    for (int kap = 0; kap < 4; ++kap)
+                        for (int lam = 0; lam < 4; ++lam) s += T[kap][lam] * conn[lam][n][kap];
+                    srcE[(size_t)(UU + n) * nz + z] = G.gdet * s;
+                }
+                if (nv == 10) {
+                    /* limited slopes of Theta, u_mu, u^i at P^E (Sec. 2.3: spatial
+                     * derivatives in the sources use the generalized minmod slope) */
+                    double dth[3] = {0, 0, 0}, ducov[3][4], ducon[3][4];
+                    memset(ducov, 0, sizeof(ducov));
+                    memset(ducon, 0, sizeof(ducon));
+                    for (int d = 0; d < nd; ++d) {
+                        size_t st = o_stride(L, d);
+                        double Xq[3][9];
+                        for (int o = -1; o <= 1; ++o) {
+                            double Xn[4], Pnb[NVMAX];
+                            int idx[3] = {i, j, k};
+                            idx[d] += o;
+                            o_zone_X(c, L, idx[0], idx[1], idx[2], Xn);
+                            ogeom_t Gn;
+                            o_geom(c, Xn, &Gn);
+                            o_get_cell(c, L, Pg, (size_t)((long)m + o * (long)st), Pnb);
+                            ostate_t Sn;
+                            o_state(c, Pnb, &Gn, &Sn);
+                            Xq[o + 1][0] = Sn.pg / Pnb[RHO];
+                            for (int mu = 0; mu < 4; ++mu) Xq[o + 1][1 + mu] = Sn.ucov[mu];
+                            for (int mu = 1; mu < 4; ++mu) Xq[o + 1][4 + mu] = Sn.ucon[mu];
+                        }
+                        double dxd = o_dx(c, d);
+                        double sl[8];
+                        for (int q = 0; q < 8; ++q)
+                            sl[q] = o_gmm(Xq[1][q] - Xq[0][q], Xq[2][q] - Xq[1][q], c->theta_plm) / dxd;
+                        dth[d] = sl[0];
+                        for (int mu = 0; mu < 4; ++mu) ducov[d][mu] = sl[1 + mu];
+                        for (int mu = 1; mu < 4; ++mu) ducon[d][mu] = sl[4 + mu];
+                    }
+                    double theta = S.pg / P[RHO];
+                    double a1 = 0.0, a2 = 0.0, divs = 0.0, b1 = 0.0, b2 = 0.0;
+                    for (int d = 0; d < nd; ++d) {
+                        a1 += S.bhcon[d + 1] * dth[d];
+                        for (int mu = 0; mu < 4; ++mu) {
+                            a2 += S.bhcon[mu] * S.ucon[d + 1] * ducov[d][mu];
+                            b1 += S.bhcon[d + 1] * S.bhcon[mu] * ducov[d][mu];
+                        }
+                        divs += ducon[d][d + 1];
+                    }
+                    double gam_a = 0.0, gam_div = 0.0, gam_b = 0.0;
+                    for (int mu = 0; mu < 4; ++mu)
+                        for (int n = 0; n < 4; ++n)
+                            for (int l = 0; l < 4; ++l) {
+                                gam_a += S.bhcon[mu] * conn[l][n][mu] * S.ucon[n] * S.ucov[l];
+                                gam_b += S.bhcon[mu] * S.bhcon[n] * conn[l][mu][n] * S.ucov[l];
+                            }
+                    for (int mu = 0; mu < 4; ++mu)
+                        for (int l = 0; l < 4; ++l) gam_div += conn[mu][mu][l] * S.ucon[l];
+                    (void)b2;
+                    sp[z].sq_sp = a1 + theta * (a2 - gam_a);
+                    sp[z].sdiv_sp = divs + gam_div;
+                    sp[z].sdp_sp = b1 - gam_b;
+                } else {
+                    sp[z].sq_sp = sp[z].sdiv_sp = sp[z].sdp_sp = 0.0;
+                }
+            }
+    for (int d = 0; d < nd; ++d) free(Fd[d]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* linear solve and Newton driver (Sec. 3)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Solve A x = b (A row-major n x n) by Gaussian elimination with partial
+ * pivoting (the factorisation LAPACK's dgesv performs).  Returns 1 on an
+ * exactly zero pivot. */
+int oracle_solve(int n, const double* A, const double* b, double* x)
+{
+    double M[16][17];
+    if (n > 16) return 2;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) M[i][j] = A[i * n + j];
+        M[i][n] = b[i];
+    }
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+        if (M[p][k] == 0.0) return 1;
+        if (p != k)
+            for (int j = 0; j <= n; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+        for (int i = k + 1; i < n; ++i) {
+            double f = M[i][k] / M[k][k];
+            for (int j = k; j <= n; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = M[i][n];
+        for (int j = i + 1; j < n; ++j) s -= M[i][j] * x[j];
+        x[i] = s / M[i][i];
+    }
+    return 0;
+}
+
+/* Quadratic backtracking step (Sec. 3.2, eq. linesearch_residual and the
+ * update that follows it): model f(lam) as a quadratic with f'(0) = -2 f(0). */
+double oracle_ls_lambda(double f0, double f1, double lam)
+{
+    return f0 * lam * lam / (f1 + (2.0 * lam - 1.0) * f0);
+}
+
+static double o_norm(int n, const double* r, double nscale)
+{
+    double s = 0.0;
+    for (int v = 0; v < n; ++v) s += r[v] * r[v];
+    return nscale * sqrt(s);
+}
+
+/* Numerical Jacobian (Sec. 3.1, eq. numerical_jacobian and the perturbation
+ * rule that follows): row i = residual component, column j = perturbed
+ * primitive,  J_ij = (R_i(P_eps,j) - R_i(P)) / (P_eps,j - P_j), where only P_j
+ * is perturbed: P_eps = (1+eps) P (1 - small) + eps small, small = [|P| < 5 eps].
+ * Reading: if the perturbation is exactly zero, P_j + eps is used.
+ * R must hold R(x) on entry; J is row-major n x n. */
+void oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x, const double* R, double eps, double* J)
+{
+    double xp[16], Rp[16];
+    for (int j = 0; j < n; ++j) {
+        for (int q = 0; q < n; ++q) xp[q] = x[q];
+        double pj = x[j];
+        double small = fabs(pj) < 5.0 * eps ? 1.0 : 0.0;
+        double pe = (1.0 + eps) * pj * (1.0 - small) + eps * small;
+        double h = pe - pj;
+        if (h == 0.0) { pe = pj + eps; h = pe - pj; }
+        xp[j] = pe;
+        fn(ctx, xp, Rp);
+        for (int i = 0; i < n; ++i) J[i * n + j] = (Rp[i] - R[i]) / h;
+    }
+}
+
+/* Newton iteration with a numerical Jacobian and backtracking (Sec. 3,
+ * eqs. newton_iters and numerical_jacobian, Sec. 3.1, Sec. 3.2), one system.
+ *  - norm: ||R|| = nscale * sqrt(sum R_v^2)
+ *  - stop when ||R|| < tol (iters = number of linear solves), or at k_max
+ *  - Jacobian by oracle_fd_jacobian
+ *  - line search: accept if ||R(P + lam dP)|| < ||R(P)|| (1 - eps_bt lam);
+ *    otherwise lam <- quadratic backtrack; a non-finite trial halves lam;
+ *    after ls_max trials the last finite trial is taken (flag LS_EXHAUSTED). */
+int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nscale, double tol, double eps,
+                          double eps_bt, int k_max, int ls_max, int32_t* iters, double* resid, uint8_t* flags)
+{
+    double R[16], J[256], dx[16], xt[16], Rt[16], negR[16];
+    uint8_t fl = 0;
+    int k = 0;
+    if (n > 16) return 2;
+    fn(ctx, x, R);
+    double r = o_norm(n, R, nscale);
+    for (;;) {
+        if (!isfinite(r)) { fl |= OFLAG_NONFINITE; break; }
+        if (r < tol) break;
+        if (k >= k_max) { fl |= OFLAG_NOT_CONVERGED; break; }
+        oracle_fd_jacobian(n, fn, ctx, x, R, eps, J);
+        for (int i = 0; i < n; ++i) negR[i] = -R[i];
+        if (oracle_solve(n, J, negR, dx) != 0) { fl |= OFLAG_SINGULAR; break; }
+        double f0 = r * r, lam = 1.0, rt = 0.0;
+        int accepted = 0, have_finite = 0;
+        double xf[16], Rf[16], rf = 0.0;
+        for (int t = 0; t < ls_max; ++t) {
+            for (int q = 0; q < n; ++q) xt[q] = x[q] + lam * dx[q];
+            fn(ctx, xt, Rt);
+            rt = o_norm(n, Rt, nscale);
+            if (isfinite(rt)) {
+                have_finite = 1;
+                for (int q = 0; q < n; ++q) { xf[q] = xt[q]; Rf[q] = Rt[q]; }
+                rf = rt;
+                if (rt < r * (1.0 - eps_bt * lam)) { accepted = 1; break; }
+                lam = oracle_ls_lambda(f0, rt * rt, lam);
+            } else {
+                lam *= 0.5;
+            }
+        }
+        if (!accepted) {
+            fl |= OFLAG_LS_EXHAUSTED;
+            if (!have_finite) { fl |= OFLAG_NONFINITE; ++k; break; }
+        }
+        for (int q = 0; q < n; ++q) { x[q] = xf[q]; R[q] = Rf[q]; }
+        r = rf;
+        ++k;
+    }
+    if (iters) *iters = k;
+    if (resid) *resid = r;
+    if (flags) *flags = fl;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the per-zone residual (Sec. 2.3 eqs. half_step, full_step; Sec. 3        */
+/* eq. half_step_residual; Sec. 4 relaxation equations)                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const ocfg_t* c;
+    ogeom_t G;
+    double dtp;
+    double Un[NVMAX];     /* U(P_n)                                         */
+    double expl[NVMAX];   /* -divF(P^E) + S^E(P^E)                           */
+    /* EMHD: time level n */
+    double theta_n, ucov_n[4], u0_n, qt_n, dpt_n;
+    /* EMHD: quantities frozen at P^E */
+    double rhoE, thetaE, u0E, qtE, dptE, bhE[4];
+    oemhd_sp_t sp;
+} ozone_t;
+
+/* R(P) = (U(P) - U(P_n))/dtp + divF(P^E) - S^E(P^E) - [implicit q, DP sources].
+ * EMHD relaxation rows (eqs. q_evol_eqn_rescaled, dP_evol_eqn_rescaled with
+ * the IMEX split of Sec. 2.3), reading of the relaxation sign as -(X-X0)/tau:
+ *   S_q = sqrt(-g) [ -(qt(P) + qt(P_n))/(2 tau) + qt0s / tau + qt(P^E)/2 divus ]
+ * where qt0s = q0s sqrt(tau/(chi rho Theta^2)) at P^E and
+ *   q0s   = -rho chi [ bhat^0 dTheta/dt + Theta bhat^mu u^0 du_mu/dt + sq_sp ]
+ *   DP0s  = 3 rho nu [ bhat^0 bhat^nu du_nu/dt + sdp_sp - divus / 3 ]
+ *   divus = du^0/dt + sdiv_sp
+ * with d X/dt = (X(P) - X(P_n))/dtp (reading of A^t dP/dt: the derived X in
+ * {Theta, u_mu, u^0} is differenced against P_n) and every coefficient,
+ * spatial derivative and connection term frozen at P^E. */
+static void o_zone_residual(void* ctx, const double* P, double* R)
+{
+    ozone_t* z = (ozone_t*)ctx;
+    const ocfg_t* c = z->c;
+    const int nv = c->nvar;
+    ostate_t S;
+    o_state(c, P, &z->G, &S);
+    double U[NVMAX];
+    o_flux_from_state(c, P, &z->G, &S, 0, U);
+    for (int v = 0; v < nv; ++v) R[v] = (U[v] - z->Un[v]) / z->dtp - z->expl[v];
+    if (nv == 10) {
+        double dtp = z->dtp;
+        double theta = S.pg / P[RHO];
+        double qt, dpt;
+        o_rescaled(c, P, &S, &qt, &dpt);
+        double dtheta = (theta - z->theta_n) / dtp;
+        double du0 = (S.ucon[0] - z->u0_n) / dtp;
+        double bdu = 0.0;
+        for (int mu = 0; mu < 4; ++mu) bdu += z->bhE[mu] * (S.ucov[mu] - z->ucov_n[mu]) / dtp;
+        double divu = du0 + z->sp.sdiv_sp;
+        double q0 = -z->rhoE * c->chi * (z->bhE[0] * dtheta + z->thetaE * z->u0E * bdu + z->sp.sq_sp);
+        double dp0 = 3.0 * z->rhoE * c->nu * (z->bhE[0] * bdu + z->sp.sdp_sp - divu / 3.0);
+        double qt0 = q0 * sqrt(c->tau_R / (c->chi * z->rhoE * z->thetaE * z->thetaE));
+        double dpt0 = dp0 * sqrt(c->tau_R / (c->nu * z->rhoE * z->thetaE));
+        double tau = c->tau_R;
+        double Sq = z->G.gdet * (-(qt + z->qt_n) / (2.0 * tau) + qt0 / tau + 0.5 * z->qtE * divu);
+        double Sd = z->G.gdet * (-(dpt + z->dpt_n) / (2.0 * tau) + dpt0 / tau + 0.5 * z->dptE * divu);
+        R[QQ] -= Sq;
+        R[DP] -= Sd;
+    }
+}
+
+static void o_zone_setup(const ocfg_t* c, const double X[4], const double* Pn, const double* PE,
+                         const double* divF_z, const double* srcE_z, const oemhd_sp_t* sp, double dtp,
+                         ozone_t* z)
+{
+    z->c = c;
+    o_geom(c, X, &z->G);
+    z->dtp = dtp;
+    ostate_t Sn;
+    o_state(c, Pn, &z->G, &Sn);
+    o_flux_from_state(c, Pn, &z->G, &Sn, 0, z->Un);
+    for (int v = 0; v < c->nvar; ++v) z->expl[v] = -divF_z[v] + srcE_z[v];
+    if (c->nvar == 10) {
+        z->theta_n = Sn.pg / Pn[RHO];
+        for (int mu = 0; mu < 4; ++mu) z->ucov_n[mu] = Sn.ucov[mu];
+        z->u0_n = Sn.ucon[0];
+        o_rescaled(c, Pn, &Sn, &z->qt_n, &z->dpt_n);
+        ostate_t SE;
+        o_state(c, PE, &z->G, &SE);
+        z->rhoE = PE[RHO];
+        z->thetaE = SE.pg / PE[RHO];
+        z->u0E = SE.ucon[0];
+        o_rescaled(c, PE, &SE, &z->qtE, &z->dptE);
+        for (int mu = 0; mu < 4; ++mu) z->bhE[mu] = SE.bhcon[mu];
+        z->sp = *sp;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* one stage of the two-stage scheme                                         */
+/* ------------------------------------------------------------------------ */
+
+int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* guess,
+                 double* Pout, int32_t* iters, double* resid, uint8_t* flags)
+{
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    olay_t L = o_layout(c);
+    const int nv = c->nvar;
+    const size_t nz = o_zones(&L);
+    double* PEg = (double*)calloc((size_t)nv * L.cells, sizeof(double));
+    double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
+    double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
+    oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
+    if (!PEg || !divF || !srcE || !sp) { free(PEg); free(divF); free(srcE); free(sp); return -1; }
+    o_to_ghosted(c, &L, PE, PEg);
+    o_explicit_stage(c, &L, PEg, divF, srcE, sp);
+
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int kk = 0; kk < L.n[2]; ++kk)
+        for (int jj = 0; jj < L.n[1]; ++jj)
+            for (int ii = 0; ii < L.n[0]; ++ii) {
+                size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX], P[NVMAX];
+                o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
+                for (int v = 0; v < nv; ++v) {
+                    pn[v] = Pn[(size_t)v * nz + z];
+                    pe[v] = PE[(size_t)v * nz + z];
+                    dz[v] = divF[(size_t)v * nz + z];
+                    sz[v] = srcE[(size_t)v * nz + z];
+                }
+                ozone_t Z;
+                o_zone_setup(c, X, pn, pe, dz, sz, &sp[z], dtp, &Z);
+                /* initial guess: P_n (or the supplied guess) with B set to the
+                 * explicit update, which is the exact root of the B rows */
+                for (int v = 0; v < nv; ++v) P[v] = guess ? guess[(size_t)v * nz + z] : pn[v];
+                for (int i = 0; i < 3; ++i)
+                    P[B1 + i] = (Z.Un[B1 + i] + dtp * Z.expl[B1 + i]) / Z.G.gdet;
+                double urho_n = Z.Un[RHO];
+                int32_t it = 0;
+                double rr = 0.0;
+                uint8_t fl = 0;
+                oracle_newton_generic(nv, o_zone_residual, &Z, P, dtp / urho_n, c->tol, c->eps, c->eps_bt,
+                                      c->k_max, c->ls_max, &it, &rr, &fl);
+                if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= OFLAG_UNPHYSICAL;
+                if (c->floors) {
+                    double r = exp(X[1]);
+                    double rf = c->rho_fl * pow(r, -1.5), uf = c->u_fl * pow(r, -2.5);
+                    if (!(P[RHO] >= rf)) P[RHO] = rf;
+                    if (!(P[UU] >= uf)) P[UU] = uf;
+                }
+                for (int v = 0; v < nv; ++v) Pout[(size_t)v * nz + z] = P[v];
+                if (iters) iters[z] = it;
+                if (resid) resid[z] = rr;
+                if (flags) flags[z] = fl;
+            }
+    free(PEg);
+    free(divF);
+    free(srcE);
+    free(sp);
+    return 0;
+}
+
+static void o_accumulate(ostats_t* st, int stage, size_t nz, const int32_t* it, const double* rr,
+                         const uint8_t* fl)
+{
+    if (!st) return;
+    st->zones = (int64_t)nz;
+    for (size_t z = 0; z < nz; ++z) {
+        st->iters_sum[stage] += it[z];
+        if (it[z] > st->max_iters) st->max_iters = it[z];
+        if (fl[z] & (OFLAG_NOT_CONVERGED | OFLAG_SINGULAR | OFLAG_NONFINITE)) st->n_fail++;
+        if (fl[z] & OFLAG_LS_EXHAUSTED) st->n_ls_exhausted++;
+        if (fl[z] & OFLAG_UNPHYSICAL) st->n_unphysical++;
+        if (rr[z] > st->max_resid || !isfinite(rr[z])) st->max_resid = rr[z];
+    }
+}
+
+/* One full step (Sec. 2.3): half step P_n -> P_{n+1/2} with P^E = P_n and
+ * dtp = dt/2, then full step P_n -> P_{n+1} with P^E = P_{n+1/2}, dtp = dt.
+ * Both solves start from P_n. */
+int oracle_step(const ocfg_t* c, double* P, double dt, ostats_t* st)
+{
+    olay_t L = o_layout(c);
+    const size_t nz = o_zones(&L);
+    const size_t nvz = (size_t)c->nvar * nz;
+    double* Ph = (double*)malloc(nvz * sizeof(double));
+    double* P1 = (double*)malloc(nvz * sizeof(double));
+    int32_t* it = (int32_t*)malloc(nz * sizeof(int32_t));
+    double* rr = (double*)malloc(nz * sizeof(double));
+    uint8_t* fl = (uint8_t*)malloc(nz);
+    int rc = -1;
+    if (Ph && P1 && it && rr && fl) {
+        rc = oracle_stage(c, P, P, 0.5 * dt, NULL, Ph, it, rr, fl);
+        o_accumulate(st, 0, nz, it, rr, fl);
+        if (rc == 0) rc = oracle_stage(c, P, Ph, dt, NULL, P1, it, rr, fl);
+        o_accumulate(st, 1, nz, it, rr, fl);
+        if (rc == 0) memcpy(P, P1, nvz * sizeof(double));
+    }
+    free(Ph);
+    free(P1);
+    free(it);
+    free(rr);
+    free(fl);
+    return rc;
+}
+
+int oracle_run(const ocfg_t* c, double* P, double dt, int nsteps, ostats_t* st)
+{
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = oracle_step(c, P, dt, st);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* The residual of every interior zone at the state P, for a stage with the
+ * given P_n, P^E and dtp; also the scaled norm used by the solver. */
+int oracle_residual(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* P, double* R,
+                    double* rnorm)
+{
+    olay_t L = o_layout(c);
+    const int nv = c->nvar;
+    const size_t nz = o_zones(&L);
+    double* PEg = (double*)calloc((size_t)nv * L.cells, sizeof(double));
+    double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
+    double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
+    oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
+    o_to_ghosted(c, &L, PE, PEg);
+    o_explicit_stage(c, &L, PEg, divF, srcE, sp);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int kk = 0; kk < L.n[2]; ++kk)
+        for (int jj = 0; jj < L.n[1]; ++jj)
+            for (int ii = 0; ii < L.n[0]; ++ii) {
+                size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX], p[NVMAX], r[NVMAX];
+                o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
+                for (int v = 0; v < nv; ++v) {
+                    pn[v] = Pn[(size_t)v * nz + z];
+                    pe[v] = PE[(size_t)v * nz + z];
+                    dz[v] = divF[(size_t)v * nz + z];
+                    sz[v] = srcE[(size_t)v * nz + z];
+                    p[v] = P[(size_t)v * nz + z];
+                }
+                ozone_t Z;
+                o_zone_setup(c, X, pn, pe, dz, sz, &sp[z], dtp, &Z);
+                o_zone_residual(&Z, p, r);
+                for (int v = 0; v < nv; ++v) R[(size_t)v * nz + z] = r[v];
+                if (rnorm) rnorm[z] = o_norm(nv, r, dtp / Z.Un[RHO]);
+            }
+    free(PEg);
+    free(divF);
+    free(srcE);
+    free(sp);
+    return 0;
+}
+
+/* divF, the explicit geometric source and the EMHD P^E-only source parts
+ * (sq_sp, sdiv_sp, sdp_sp per zone) for a state PE. */
+int oracle_explicit(const ocfg_t* c, const double* PE, double* divF, double* srcE, double* emhd_sp)
+{
+    olay_t L = o_layout(c);
+    const size_t nz = o_zones(&L);
+    double* PEg = (double*)calloc((size_t)c->nvar * L.cells, sizeof(double));
+    oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
+    o_to_ghosted(c, &L, PE, PEg);
+    o_explicit_stage(c, &L, PEg, divF, srcE, sp);
+    if (emhd_sp)
+        for (size_t z = 0; z < nz; ++z) {
+            emhd_sp[3 * z + 0] = sp[z].sq_sp;
+            emhd_sp[3 * z + 1] = sp[z].sdiv_sp;
+            emhd_sp[3 * z + 2] = sp[z].sdp_sp;
+        }
+    free(PEg);
+    free(sp);
+    return 0;
+}
+
+/* Time step from the CFL condition on zone-centre speeds:
+ * dt = cfl * min_zones 1 / sum_d (c_max^d / dX^d). */
+double oracle_cfl_dt(const ocfg_t* c, const double* P, double cfl)
+{
+    olay_t L = o_layout(c);
+    const size_t nz = o_zones(&L);
+    double best = 1e300;
+    for (int kk = 0; kk < L.n[2]; ++kk)
+        for (int jj = 0; jj < L.n[1]; ++jj)
+            for (int ii = 0; ii < L.n[0]; ++ii) {
+                size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                double X[4], p[NVMAX];
+                o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
+                for (int v = 0; v < c->nvar; ++v) p[v] = P[(size_t)v * nz + z];
+                ogeom_t G;
+                o_geom(c, X, &G);
+                ostate_t S;
+                o_state(c, p, &G, &S);
+                double s = 0.0;
+                for (int d = 0; d < c->ndim; ++d) {
+                    double lp, lm;
+                    o_speeds_state(c, p, &G, &S, d + 1, &lp, &lm);
+                    s += fmax(fabs(lp), fabs(lm)) / o_dx(c, d);
+                }
+                double t = 1.0 / s;
+                if (t < best) best = t;
+            }
+    return cfl * best;
+}
+
+/* Corner-centred divergence of sqrt(-g) B (the discrete constraint flux-CT
+ * preserves, Sec. 4.2) at every interior corner (i-1/2, j-1/2[, k-1/2]),
+ * i.e. for i in [1, n1), j in [1, n2)[, k in [1, n3)] of the interior grid:
+ * divb has n1*n2*n3 entries, the entries with a zero index are set to 0. */
+int oracle_divb(const ocfg_t* c, const double* P, double* divb)
+{
+    olay_t L = o_layout(c);
+    const size_t nz = o_zones(&L);
+    const int nd = c->ndim;
+    if (nd < 2) return 1;
+    for (int k = 0; k < L.n[2]; ++k)
+        for (int j = 0; j < L.n[1]; ++j)
+            for (int i = 0; i < L.n[0]; ++i) {
+                size_t z = ((size_t)k * L.n[1] + j) * L.n[0] + i;
+                divb[z] = 0.0;
+                if (i == 0 || j == 0 || (nd == 3 && k == 0)) continue;
+                double s = 0.0;
+                int nk = nd == 3 ? 2 : 1;
+                for (int d = 0; d < nd; ++d) {
+                    double acc = 0.0;
+                    for (int ok = 0; ok < nk; ++ok)
+                        for (int oj = 0; oj < 2; ++oj)
+                            for (int oi = 0; oi < 2; ++oi) {
+                                int ci = i - 1 + oi, cj = j - 1 + oj, ck = nd == 3 ? k - 1 + ok : k;
+                                int o[3] = {oi, oj, ok};
+                                double sgn = o[d] ? 1.0 : -1.0;
+                                double X[4];
+                                o_zone_X(c, &L, ci + L.g[0], cj + L.g[1], ck + L.g[2], X);
+                                ogeom_t G;
+                                o_geom(c, X, &G);
+                                size_t zz = ((size_t)ck * L.n[1] + cj) * L.n[0] + ci;
+                                acc += sgn * G.gdet * P[(size_t)(B1 + d) * nz + zz];
+                            }
+                    s += acc / ((nd == 3 ? 4.0 : 2.0) * o_dx(c, d));
+                }
+                divb[z] = s;
+            }
+    return 0;
+}
+
+/* Sum over interior zones of U(P) (times the zone volume in X). */
+int oracle_sum_U(const ocfg_t* c, const double* P, double* sums)
+{
+    olay_t L = o_layout(c);
+    const size_t nz = o_zones(&L);
+    double vol = c->dx1 * (c->ndim >= 2 ? c->dx2 : 1.0) * (c->ndim >= 3 ? c->dx3 : 1.0);
+    for (int v = 0; v < c->nvar; ++v) sums[v] = 0.0;
+    for (int k = 0; k < L.n[2]; ++k)
+        for (int j = 0; j < L.n[1]; ++j)
+            for (int i = 0; i < L.n[0]; ++i) {
+                size_t z = ((size_t)k * L.n[1] + j) * L.n[0] + i;
+                double X[4], p[NVMAX], U[NVMAX];
+                o_zone_X(c, &L, i + L.g[0], j + L.g[1], k + L.g[2], X);
+                for (int v = 0; v < c->nvar; ++v) p[v] = P[(size_t)v * nz + z];
+                ogeom_t G;
+                o_geom(c, X, &G);
+                ostate_t S;
+                o_state(c, p, &G, &S);
+                o_flux_from_state(c, p, &G, &S, 0, U);
+                for (int v = 0; v < c->nvar; ++v) sums[v] += U[v] * vol;
+            }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* point functions exported for the pins                                     */
+/* ------------------------------------------------------------------------ */
+
+void oracle_geometry(const ocfg_t* c, const double* X, double* gcov, double* gcon, double* gdet, double* alpha)
+{
+    ogeom_t G;
+    o_geom(c, X, &G);
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) {
+            gcov[4 * m + n] = G.gcov[m][n];
+            gcon[4 * m + n] = G.gcon[m][n];
+        }
+    *gdet = G.gdet;
+    *alpha = G.alpha;
+}
+
+void oracle_connection(const ocfg_t* c, const double* X, double* conn)
+{
+    double C[4][4][4];
+    o_conn(c, X, C);
+    memcpy(conn, C, sizeof(C));
+}
+
+void oracle_prim_to_flux(const ocfg_t* c, const double* P, const double* X, int dir, double* out)
+{
+    ogeom_t G;
+    o_geom(c, X, &G);
+    ostate_t S;
+    o_state(c, P, &G, &S);
+    o_flux_from_state(c, P, &G, &S, dir, out);
+}
+
+void oracle_speeds(const ocfg_t* c, const double* P, const double* X, int dir, double* lp, double* lm)
+{
+    ogeom_t G;
+    o_geom(c, X, &G);
+    ostate_t S;
+    o_state(c, P, &G, &S);
+    o_speeds_state(c, P, &G, &S, dir, lp, lm);
+}
+
+double oracle_vmax2(const ocfg_t* c, const double* P, const double* X)
+{
+    ogeom_t G;
+    o_geom(c, X, &G);
+    ostate_t S;
+    o_state(c, P, &G, &S);
+    return o_vmax2_state(c, P, &S);
+}
+
+/* Finite-difference Jacobian of the residual of one interior zone (index z in
+ * the interior ordering) at state P, for a stage with P_n, P^E and dtp. */
+int oracle_zone_jacobian(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* P,
+                         long z, double* J, double* Rz)
+{
+    olay_t L = o_layout(c);
+    const int nv = c->nvar;
+    const size_t nz = o_zones(&L);
+    if (z < 0 || (size_t)z >= nz) return 1;
+    double* PEg = (double*)calloc((size_t)nv * L.cells, sizeof(double));
+    double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
+    double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
+    oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
+    o_to_ghosted(c, &L, PE, PEg);
+    o_explicit_stage(c, &L, PEg, divF, srcE, sp);
+    int ii = (int)(z % L.n[0]), jj = (int)((z / L.n[0]) % L.n[1]), kk = (int)(z / ((size_t)L.n[0] * L.n[1]));
+    double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX], p[NVMAX];
+    o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
+    for (int v = 0; v < nv; ++v) {
+        pn[v] = Pn[(size_t)v * nz + z];
+        pe[v] = PE[(size_t)v * nz + z];
+        dz[v] = divF[(size_t)v * nz + z];
+        sz[v] = srcE[(size_t)v * nz + z];
+        p[v] = P[(size_t)v * nz + z];
+    }
+    ozone_t Z;
+    o_zone_setup(c, X, pn, pe, dz, sz, &sp[z], dtp, &Z);
+    o_zone_residual(&Z, p, Rz);
+    oracle_fd_jacobian(nv, o_zone_residual, &Z, p, Rz, c->eps, J);
+    free(PEg);
+    free(divF);
+    free(srcE);
+    free(sp);
+    return 0;
+}

@@ -1,0 +1,97 @@
+/*
+ * Plain FP64 CPU oracle of the grim method (Chandra, Foucart & Gammie,
+ * "grim: A Flexible, Conservative Scheme for Relativistic Fluid Theories").
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only code that may load this
+ * library.  The GPU library neither links nor includes anything from here,
+ * and nothing here includes anything from the GPU library.
+ *
+ * Arrays of primitives are structure-of-arrays, [nvar][n3][n2][n1] for the
+ * interior-only API, i fastest.  Primitive order (Sec. 4, closing summary):
+ *   0 rho, 1 u, 2..4 normal-observer four-velocity utilde^i, 5..7 B^i,
+ *   8 q, 9 DeltaP (EMHD only).
+ */
+#ifndef GRIM_ORACLE_H
+#define GRIM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int ndim;              /* 1, 2 or 3 active directions (X1, X1-X2, X1-X3) */
+    int n1, n2, n3;        /* interior zones (inactive directions: 1)       */
+    int ng;                /* ghost layers on each side of active directions */
+    int nvar;              /* 8 ideal MHD, 10 EMHD                            */
+    int metric;            /* 0 Minkowski Cartesian, 1 modified Kerr-Schild  */
+    int bc1, bc2, bc3;     /* 0 periodic, 1 outflow copy, 2 polar reflection */
+    double x1s, x2s, x3s;  /* start of the domain in X^i                      */
+    double dx1, dx2, dx3;  /* zone widths in X^i                              */
+    double spin, hslope;   /* Kerr spin a, mid-plane refinement h             */
+    double gam;            /* adiabatic index                                 */
+    double tau_R, chi, nu; /* EMHD relaxation time and diffusivities          */
+    double theta_plm;      /* generalized-minmod parameter                    */
+    double tol, eps, eps_bt;
+    int k_max, ls_max;
+    int floors;            /* 1: rho >= rho_fl r^-3/2, u >= u_fl r^-5/2        */
+    double rho_fl, u_fl;
+    int nthreads;          /* OpenMP threads, 0 = runtime default             */
+} ocfg_t;
+
+typedef struct {
+    double iters_sum[2];   /* per stage: sum of Newton iterations            */
+    int64_t zones;         /* interior zones per stage                       */
+    int32_t max_iters;
+    int64_t n_fail;        /* zones with NOT_CONVERGED/SINGULAR/NONFINITE    */
+    int64_t n_ls_exhausted;
+    int64_t n_unphysical;
+    double max_resid;
+} ostats_t;
+
+/* per-zone flags */
+#define OFLAG_NOT_CONVERGED 1
+#define OFLAG_LS_EXHAUSTED  2
+#define OFLAG_SINGULAR      4
+#define OFLAG_UNPHYSICAL    8
+#define OFLAG_NONFINITE     16
+
+int    oracle_stage(const ocfg_t* c, const double* Pn, const double* PE,
+                    double dtp, const double* guess, double* Pout,
+                    int32_t* iters, double* resid, uint8_t* flags);
+int    oracle_step(const ocfg_t* c, double* P, double dt, ostats_t* st);
+int    oracle_run(const ocfg_t* c, double* P, double dt, int nsteps, ostats_t* st);
+int    oracle_residual(const ocfg_t* c, const double* Pn, const double* PE,
+                       double dtp, const double* P, double* R, double* rnorm);
+int    oracle_explicit(const ocfg_t* c, const double* PE, double* divF,
+                       double* srcE, double* emhd_sp);
+double oracle_cfl_dt(const ocfg_t* c, const double* P, double cfl);
+void   oracle_geometry(const ocfg_t* c, const double* X, double* gcov,
+                       double* gcon, double* gdet, double* alpha);
+void   oracle_connection(const ocfg_t* c, const double* X, double* conn);
+void   oracle_prim_to_flux(const ocfg_t* c, const double* P, const double* X,
+                           int dir, double* out);
+void   oracle_speeds(const ocfg_t* c, const double* P, const double* X, int dir,
+                     double* lp, double* lm);
+double oracle_vmax2(const ocfg_t* c, const double* P, const double* X);
+int    oracle_solve(int n, const double* A, const double* b, double* x);
+double oracle_ls_lambda(double f0, double f1, double lam);
+typedef void (*oresid_fn)(void* ctx, const double* x, double* r);
+int    oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x,
+                             double nscale, double tol, double eps,
+                             double eps_bt, int k_max, int ls_max,
+                             int32_t* iters, double* resid, uint8_t* flags);
+void   oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x,
+                          const double* R, double eps, double* J);
+int    oracle_zone_jacobian(const ocfg_t* c, const double* Pn, const double* PE,
+                            double dtp, const double* P, long z, double* J,
+                            double* Rz);
+int    oracle_divb(const ocfg_t* c, const double* P, double* divb);
+int    oracle_sum_U(const ocfg_t* c, const double* P, double* sums);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
