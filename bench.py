@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the grim per-zone Newton method on one MI355X.
+
+Metric: zone-updates per second at Newton residual 1e-10 (one zone-update =
+one interior zone advanced one full two-stage step), with the mean Newton
+iterations per zone and stage, on the 2D EMHD workload (256 x 256 zones, 10
+FP64 primitives, 16 seeded Fourier modes in rho and u, 50 steps, plain FP64
+Newton).  Inputs are synthetic and resident in HBM before the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+One "step" is one full time step (both stages: ghost fill, PLM/LLF fluxes,
+flux-CT, stage right-hand side, Newton solve) over the whole grid, replayed
+from a captured HIP graph.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, dense
+HBM_PEAK_GBS = 8000.0
+
+# FP64 operations (fma = 2, sqrt = div = 1) of one residual evaluation R(P)
+# in Minkowski coordinates, counted on the specialised register code: derive
+# the state, T^0_nu, U(P), and for EMHD the rescaled q, DP and the implicit
+# relaxation terms.  Norm: 2N + 2.  Jacobian column: perturbation (4), the
+# reciprocal of h (1), N subtractions and N multiplications.  LU with partial
+# pivoting and one right-hand side: 2N^3/3 + 2N^2 (rounded, below).
+RESID_FLOPS = {8: 66, 10: 157}
+LU_FLOPS = {8: 469, 10: 867}
+
+
+def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) -> float:
+    """Algorithmic FP64 flops of the Newton solves summed over a run."""
+    n = nvar
+    ls_trials = resid_calls - zone_stages - n * iters
+    norm = 2 * n + 2
+    return (resid_calls * RESID_FLOPS[n]
+            + (zone_stages + ls_trials) * norm
+            + iters * (n * (2 * n + 5) + LU_FLOPS[n])
+            + ls_trials * 2 * n)
+
+
+def _source_hash(path: str) -> str:
+    h = hashlib.sha256()
+    with open(path, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_src: str):
+    """HBM bytes per Newton launch from committed rocprofv3 counters, if they
+    were taken on the current kernel source; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "newton_emhd2d_256_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != _source_hash(kernel_src):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(wl: dict, P0, dt: float, steps: int) -> dict:
+    import oracle
+
+    threads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        threads = min(threads, int(env))
+    o = oracle.Oracle(dict(wl, nthreads=threads))
+    t0 = time.perf_counter()
+    _, st = o.step(P0, dt, steps)
+    t = time.perf_counter() - t0
+    zones = P0[0].size
+    return {
+        "value": zones * steps / t,
+        "unit": "zone-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {steps} of the {wl['steps']} steps of the same workload, full grid",
+        "seconds": t,
+        "mean_iters": st["mean_iters"],
+    }
+
+
+def timed_run(grim, W, wl, P0, steps, warmup):
+    import torch
+
+    ctx = grim.Context(wl)
+    ctx.set_prims(P0)
+    dt = ctx.cfl_dt(wl["cfl"])
+    if warmup > 0:
+        ctx.run(dt, warmup, use_graph=True)
+    ctx.set_prims(P0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.run(dt, steps, use_graph=True, want_stats=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # instrumented eager pass over the same steps: per-kernel device time
+    ctx.set_prims(P0)
+    ctx.profile(True)
+    st_p = ctx.run(dt, steps, use_graph=False, want_stats=True)
+    times = ctx.kernel_times()
+    ctx.profile(False)
+    ctx.close()
+    return dt, t, st, st_p, times
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="emhd2d_modes_256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU halo exchange is not built",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1702_01106_amd import grim
+    from paper_1702_01106_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 2
+    grim.load()  # raises if the HIP library is missing: no fallback
+    wl = W.workload(args.workload)
+    P0 = W.initial_state(wl, seed=0)
+    zones = int(P0[0].size)
+    nvar = wl["nvar"]
+
+    dt, t, st, st_p, times = timed_run(grim, W, wl, P0, args.steps, args.warmup)
+    value = zones * args.steps / t
+    ms_newton, n_newton = times["newton"]
+    flops = newton_flops(nvar, st_p["zone_stages"], (st_p["mean_iters"][0] + st_p["mean_iters"][1]) * zones
+                         * args.steps, st_p["n_resid_calls"])
+    per_launch_flops = flops / max(n_newton, 1)
+    avg_s = ms_newton / max(n_newton, 1) * 1e-3
+    achieved = per_launch_flops / avg_s / 1e12
+    kernel_src = os.path.join(ROOT, "paper_1702_01106_amd", "csrc", "newton.hip")
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS,
+        "traffic": traffic_from_profiles(kernel_src),
+        "kernel": f"k_newton<{nvar}, Minkowski, f64>",
+        "avg_launch_us": avg_s * 1e6,
+        "flops_per_launch": per_launch_flops,
+    }
+    out = {
+        "metric": "zone-updates/sec at Newton residual 1e-10; mean Newton iters/zone; vs FP64 GPU",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "zones": zones, "nvar": nvar, "steps_in_workload": wl["steps"],
+                   "tol": wl["tol"], "jacobian": "f64", "dt": dt},
+        "mean_newton_iters": st["mean_iters"],
+        "max_resid": st["max_resid"],
+        "n_fail": st["n_fail"],
+        "kernel_ms": {k: v[0] for k, v in times.items()},
+        "roofline": roofline,
+    }
+    if not args.no_variants:
+        wl32 = dict(wl, jac="f32")
+        _, t32, st32, _, times32 = timed_run(grim, W, wl32, P0, args.steps, args.warmup)
+        out["variants"] = {
+            "f32_jacobian_lu": {
+                "value": zones * args.steps / t32,
+                "ms_per_step": t32 / args.steps * 1e3,
+                "mean_newton_iters": st32["mean_iters"],
+                "max_resid": st32["max_resid"],
+                "n_fail": st32["n_fail"],
+                "newton_avg_launch_us": times32["newton"][0] / max(times32["newton"][1], 1) * 1e3,
+                "speedup_vs_f64": (zones * args.steps / t32) / value,
+            }
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, P0, dt, args.cpu_steps)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,185 @@
+/*
+ * libgrim -- MI355X (gfx950) implementation of the per-zone Newton-Raphson
+ * method of Chandra, Foucart & Gammie, "grim: A Flexible, Conservative Scheme
+ * for Relativistic Fluid Theories" (arXiv:1702.01106).
+ *
+ * The library advances relativistic ideal MHD (8 primitives) or extended MHD
+ * (EMHD, 10 primitives) on a uniform grid in coordinates X^i with a
+ * Minkowski or modified Kerr-Schild metric (Sec. 2.1).  One step is the
+ * two-stage semi-implicit scheme of Sec. 2.3: each stage computes the
+ * explicit fluxes at P^E (PLM reconstruction, LLF, flux-CT; Sec. 2.4, 4.2)
+ * and then solves the discrete equations for the primitives of every zone
+ * by Newton's method with a finite-difference Jacobian, a dense per-zone LU
+ * solve and a quadratic backtracking line search (Sec. 3).
+ *
+ * Conventions
+ *  - Primitive order (Sec. 4): rho, u, utilde^1..3 (normal-observer
+ *    four-velocity, equal to u^i in Minkowski), B^1..3, and for EMHD q and
+ *    DeltaP.
+ *  - Arrays of primitives are FP64, structure of arrays, interior zones only:
+ *    P[v][k][j][i] with i fastest, v in [0, nvar), sizes n3 x n2 x n1 (n2 = 1
+ *    and n3 = 1 in 1D, n3 = 1 in 2D).
+ *  - Pointers: the test hooks take device pointers (memory the caller owns,
+ *    e.g. from PyTorch).  grim_set_prims / grim_get_prims take a flag that
+ *    says whether the pointer is host or device memory.  The library never
+ *    keeps a caller pointer after a call returns.
+ *  - Every call returns GRIM_OK (0) or a negative GRIM_E_* code; the message
+ *    is available from grim_last_error (per context) or
+ *    grim_last_global_error (for failures of grim_create).  No C++ exception
+ *    crosses the interface.  Per-zone non-convergence is not an error: it is
+ *    reported in the per-zone flags and in grim_stats_t.
+ *  - Work is enqueued on the stream given at create time (NULL: the null
+ *    stream).  Calls that return data to the host synchronise that stream.
+ *  - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef GRIM_H
+#define GRIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRIM_OK 0
+#define GRIM_E_INVALID_ARG (-1)
+#define GRIM_E_HIP (-2)
+#define GRIM_E_OOM (-3)
+#define GRIM_E_STATE (-4)
+
+/* models: number of primitives */
+#define GRIM_IDEAL_MHD 8
+#define GRIM_EMHD 10
+/* metrics */
+#define GRIM_MINKOWSKI 0
+#define GRIM_MKS_KERR 1
+/* boundary conditions, per direction */
+#define GRIM_BC_PERIODIC 0
+#define GRIM_BC_OUTFLOW 1
+#define GRIM_BC_POLAR 2
+/* precision of the Jacobian difference quotients, storage and LU */
+#define GRIM_JAC_F64 0
+#define GRIM_JAC_F32 1
+/* per-zone flags */
+#define GRIM_FLAG_NOT_CONVERGED 1
+#define GRIM_FLAG_LS_EXHAUSTED 2
+#define GRIM_FLAG_SINGULAR 4
+#define GRIM_FLAG_UNPHYSICAL 8
+#define GRIM_FLAG_NONFINITE 16
+
+typedef struct grim_ctx grim_ctx_t;
+
+/* Problem and solver description, copied at create (plain value struct). */
+typedef struct {
+    int ndim;            /* 1, 2 or 3 active directions                      */
+    int n1, n2, n3;      /* interior zones per direction (1 if inactive)     */
+    int ng;              /* ghost layers per side of active directions (2)   */
+    int model;           /* GRIM_IDEAL_MHD or GRIM_EMHD                      */
+    int metric;          /* GRIM_MINKOWSKI or GRIM_MKS_KERR                  */
+    double x_start[3];   /* domain in X^i (Sec. 2.1)                         */
+    double x_end[3];
+    double spin_a;       /* Kerr spin a                                      */
+    double mks_h;        /* mid-plane refinement h of eq. theta_transform    */
+    int bc[3];           /* GRIM_BC_* per direction                          */
+    double gamma;        /* adiabatic index, P = (gamma - 1) u               */
+    double tau_R;        /* EMHD relaxation time (Sec. 4)                    */
+    double chi, nu;      /* EMHD thermal and viscous diffusivities           */
+    double plm_theta;    /* generalized-minmod parameter (Sec. 2.3, 2.4.1)   */
+    double tol;          /* Newton tolerance on the scaled norm              */
+    double eps_fd;       /* Jacobian differencing parameter (Sec. 3.1)       */
+    double eps_bt;       /* line-search acceptance parameter (Sec. 3.2)      */
+    int k_max;           /* maximum Newton iterations                        */
+    int ls_max;          /* maximum line-search trials per iteration         */
+    int jac_precision;   /* GRIM_JAC_F64 or GRIM_JAC_F32                     */
+    int floors;          /* 1: rho >= rho_floor r^-3/2, u >= u_floor r^-5/2   */
+    double rho_floor, u_floor;
+} grim_config_t;
+
+/* Per-call solver statistics (a13).  mean_iters is per zone per stage. */
+typedef struct {
+    double mean_iters[2];   /* stage 1 (half step), stage 2 (full step)      */
+    int32_t max_iters;
+    int32_t pad;
+    int64_t n_fail;         /* zones flagged NOT_CONVERGED, SINGULAR or NONFINITE */
+    int64_t n_ls_exhausted;
+    int64_t n_unphysical;
+    double max_resid;       /* largest final scaled residual norm            */
+    int64_t zone_stages;    /* zones x stages accumulated                    */
+    int64_t n_resid_calls;  /* residual evaluations R(P), summed over zones  */
+} grim_stats_t;
+
+/* Create a context: validates cfg, allocates device buffers (ghosted
+ * primitive arrays, face fluxes, edge EMFs, stage right-hand sides, per-zone
+ * results, metric tables) and builds the metric tables (a1, Sec. 2.1).
+ * hip_stream: a hipStream_t owned by the caller, or NULL.
+ * Errors: GRIM_E_INVALID_ARG (bad sizes or parameters), GRIM_E_OOM, GRIM_E_HIP. */
+int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out);
+int grim_destroy(grim_ctx_t* ctx);
+const char* grim_last_error(const grim_ctx_t* ctx);
+const char* grim_last_global_error(void);
+
+/* Device bytes the context holds (for capacity planning). */
+size_t grim_device_bytes(const grim_ctx_t* ctx);
+
+/* Copy the interior primitives in (set) or out (get).  on_device != 0 means P
+ * is device memory.  Synchronises the stream. */
+int grim_set_prims(grim_ctx_t* ctx, const double* P, int on_device);
+int grim_get_prims(grim_ctx_t* ctx, double* P, int on_device);
+
+/* dt = cfl * min over zones of 1 / sum_d (c_max^d / dX^d), with c_max^d the
+ * largest |grid-frame speed| of the zone-centre state (Sec. 4.1).
+ * Synchronises the stream. */
+int grim_cfl_dt(grim_ctx_t* ctx, double cfl, double* dt);
+
+/* Advance nsteps full steps of size dt (Sec. 2.3: half step with P^E = P_n,
+ * dt' = dt/2, then full step with P^E = P_{n+1/2}, dt' = dt; both Newton
+ * solves start from P_n with B at its explicit update).  Asynchronous unless
+ * stats != NULL, in which case the statistics of these steps are returned.
+ * use_graph != 0 replays the step from a captured HIP graph. */
+int grim_run(grim_ctx_t* ctx, double dt, int nsteps, int use_graph, grim_stats_t* stats);
+
+/* Test hook for a8: the residual R(P) of every interior zone for a stage with
+ * P_n, P^E and dt' (eqs. half_step_residual / full_step), and the scaled norm
+ * ||R|| = sqrt(sum_v (dt' R_v)^2) / U_rho(P_n).  All pointers device, interior
+ * layout; rnorm may be NULL. */
+int grim_residual(grim_ctx_t* ctx, const double* Pn, const double* PE, double dtp,
+                  const double* P, double* R, double* rnorm);
+
+/* Test hook for a2-a12: one stage.  Flux stage on P^E, then the Newton solve
+ * from guess (NULL: P_n) with B at its explicit update.  Outputs per zone:
+ * P_out (interior layout), iterations, final scaled norm and flags; any of
+ * iters / resid / flags may be NULL.  All pointers device. */
+int grim_stage_solve(grim_ctx_t* ctx, const double* Pn, const double* PE, double dtp,
+                     const double* guess, double* P_out, int32_t* iters, double* resid,
+                     uint8_t* flags);
+
+/* Test hook for a2-a6: divF (eq. fvm_formulation, with flux-CT), the explicit
+ * geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E (eq. divT_explicit)
+ * and, for EMHD, the three P^E-only source parts per zone (spatial-derivative
+ * and connection parts of the q0 and DeltaP0 targets and of div u).
+ * divF, srcE: [nvar][zones]; emhd_sp: [zones][3] or NULL.  Device pointers. */
+int grim_explicit(grim_ctx_t* ctx, const double* PE, double* divF, double* srcE,
+                  double* emhd_sp);
+
+/* Per-zone flags (GRIM_FLAG_*) and iteration counts of the last stage-2
+ * solve (or last grim_stage_solve).  on_device as for grim_set_prims. */
+int grim_get_zone_results(grim_ctx_t* ctx, uint8_t* flags, int32_t* iters, int on_device);
+
+/* Kernel timing for the roofline measurement.  While enabled, grim_run
+ * enqueues steps eagerly (no graph) and brackets every launch group with HIP
+ * events on the context's stream.  grim_kernel_times synchronises and returns,
+ * per kernel group, the summed device time in ms and the number of launches,
+ * then clears the records.  Groups: 0 ghost fill, 1 face fluxes, 2 flux-CT
+ * EMFs, 3 stage right-hand side, 4 Newton solve (n = 5 entries). */
+int grim_profile(grim_ctx_t* ctx, int enable);
+int grim_kernel_times(grim_ctx_t* ctx, double* ms, int64_t* launches, int n);
+
+/* STREAM c = a + b over n doubles (the sustained-bandwidth yardstick of
+ * Sec. 7.2).  a, b, c device pointers.  Enqueued, not timed. */
+int grim_stream_add(grim_ctx_t* ctx, const double* a, const double* b, double* c, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -115,8 +115,9 @@ static double o_inv4(const double A[4][4], double Ai[4][4])
  * Modified Kerr-Schild: Kerr in Kerr-Schild (t, r, theta, phi), mapped with
  * r = exp(X1), theta = pi X2 + (1-h)/2 sin(2 pi X2), phi = X3 (Sec. 2.1),
  * g_{mu nu}(X) = g_{ab}(x) L^a_mu L^b_nu with L = diag(1, r, dtheta/dX2, 1).
- * Reading: theta is kept at least 1e-12 away from the poles so that the
- * inverse metric stays finite on the polar faces (sqrt(-g) ~ 1e-12 there). */
+ * Reading: near the axis sin^2(theta) is kept >= 1e-24 so that the inverse
+ * metric stays finite on the polar faces; theta itself is not clamped, so
+ * ghost zones across the axis see the mirror image of the metric. */
 static void o_metric_cov(const ocfg_t* c, const double X[4], double g[4][4])
 {
     memset(g, 0, sizeof(double) * 16);
@@ -127,11 +128,10 @@ static void o_metric_cov(const ocfg_t* c, const double X[4], double g[4][4])
     const double a = c->spin, h = c->hslope;
     double r = exp(X[1]);
     double th = M_PI * X[2] + 0.5 * (1.0 - h) * sin(2.0 * M_PI * X[2]);
-    if (th < 1e-12) th = 1e-12;
-    if (th > M_PI - 1e-12) th = M_PI - 1e-12;
     double dr_dX1 = r;
     double dth_dX2 = M_PI * (1.0 + (1.0 - h) * cos(2.0 * M_PI * X[2]));
     double cth = cos(th), sth = sin(th), s2 = sth * sth;
+    if (s2 < 1e-24) s2 = 1e-24;
     double Sig = r * r + a * a * cth * cth;
     double ks[4][4];
     memset(ks, 0, sizeof(ks));

@@ -1,0 +1,603 @@
+// Host side of libgrim's C ABI (declared in include/grim.h): context
+// lifetime, buffer management, the two-stage step and the test hooks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "grim.h"
+#include "grim_internal.h"
+
+using grim::DevStats;
+using grim::Layout;
+using grim::NewtonArgs;
+using grim::Phys;
+using grim::StageArgs;
+
+struct grim_ctx {
+    grim_config_t cfg{};
+    Layout L{};
+    Phys ph{};
+    int nvar = 0;
+    hipStream_t st = nullptr;       // work stream (caller's, or owned)
+    bool own_st = false;
+    hipStream_t cap = nullptr;      // private stream used only for graph capture
+    double* P[2] = {nullptr, nullptr};  // ghosted state buffers (ping-pong)
+    int cur = 0;                         // buffer holding the current state
+    double* F[3] = {nullptr, nullptr, nullptr};
+    double* E[3] = {nullptr, nullptr, nullptr};
+    double* rhs = nullptr;
+    double* coef = nullptr;
+    double* interior = nullptr;          // staging buffer, interior layout
+    double* hookP[2] = {nullptr, nullptr};
+    int32_t* iters = nullptr;
+    double* resid = nullptr;
+    uint8_t* flags = nullptr;
+    DevStats* stats = nullptr;
+    unsigned long long* u64 = nullptr;
+    double* geo_centre = nullptr;
+    double* geo_face[3] = {nullptr, nullptr, nullptr};
+    double* geo_conn = nullptr;
+    size_t bytes = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    double graph_dt = 0.0;
+    bool timing = false;
+    struct Mark {
+        int group;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(grim_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_last_error = msg;
+    return code;
+}
+
+int hip_fail(grim_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, GRIM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                        \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #expr);  \
+    } while (0)
+
+template <typename T>
+int dalloc(grim_ctx* c, T** p, size_t count)
+{
+    const size_t b = count * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, b);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? GRIM_E_OOM : GRIM_E_HIP,
+                    std::string("hipMalloc(") + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+    }
+    c->bytes += b;
+    return GRIM_OK;
+}
+
+void release(grim_ctx* c)
+{
+    for (auto& m : c->marks) {
+        hipEventDestroy(m.a);
+        hipEventDestroy(m.b);
+    }
+    c->marks.clear();
+    for (int i = 0; i < 2; ++i)
+        if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
+    if (c->cap) hipStreamDestroy(c->cap);
+    if (c->own_st && c->st) hipStreamDestroy(c->st);
+    void* ptrs[] = {c->P[0], c->P[1], c->F[0], c->F[1], c->F[2], c->E[0], c->E[1], c->E[2], c->rhs, c->coef,
+                    c->interior, c->hookP[0], c->hookP[1], c->iters, c->resid, c->flags, c->stats, c->u64,
+                    c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+}
+
+int validate(const grim_config_t* g, std::string& why)
+{
+    if (g->ndim < 1 || g->ndim > 3) return why = "ndim must be 1, 2 or 3", 1;
+    const int n[3] = {g->n1, g->n2, g->n3};
+    for (int d = 0; d < 3; ++d) {
+        if (d < g->ndim && n[d] < 1) return why = "active direction with no zones", 1;
+        if (d >= g->ndim && n[d] != 1) return why = "inactive direction must have n = 1", 1;
+    }
+    if (g->ng != 2) return why = "ng must be 2 (PLM and flux-CT stencils)", 1;
+    if (g->model != GRIM_IDEAL_MHD && g->model != GRIM_EMHD) return why = "model must be 8 or 10", 1;
+    if (g->metric != GRIM_MINKOWSKI && g->metric != GRIM_MKS_KERR) return why = "unknown metric", 1;
+    if (g->metric == GRIM_MKS_KERR && g->ndim < 2) return why = "Kerr needs ndim >= 2", 1;
+    for (int d = 0; d < 3; ++d) {
+        if (g->bc[d] < 0 || g->bc[d] > 2) return why = "unknown boundary condition", 1;
+        if (g->bc[d] == GRIM_BC_POLAR && d != 1) return why = "polar boundary only in X2", 1;
+        if (d < g->ndim && !(g->x_end[d] > g->x_start[d])) return why = "empty domain", 1;
+        if (d < g->ndim && n[d] < 2) return why = "active directions need n >= 2 (ghost maps read interior)", 1;
+    }
+    if (!(g->gamma > 1.0)) return why = "gamma must exceed 1", 1;
+    if (g->model == GRIM_EMHD && !(g->tau_R > 0 && g->chi > 0 && g->nu > 0))
+        return why = "EMHD needs tau_R, chi, nu > 0", 1;
+    if (!(g->tol > 0) || !(g->eps_fd > 0) || !(g->eps_bt >= 0)) return why = "bad tolerances", 1;
+    if (g->k_max < 0 || g->ls_max < 1) return why = "k_max >= 0 and ls_max >= 1 required", 1;
+    if (g->jac_precision != GRIM_JAC_F64 && g->jac_precision != GRIM_JAC_F32) return why = "bad jac_precision", 1;
+    const double zones = (double)n[0] * n[1] * n[2];
+    if (zones > 2.0e9) return why = "too many zones", 1;
+    return 0;
+}
+
+StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)
+{
+    StageArgs a{};
+    a.L = c->L;
+    a.ph = c->ph;
+    a.geo.centre = c->geo_centre;
+    for (int d = 0; d < 3; ++d) a.geo.face[d] = c->geo_face[d];
+    a.geo.conn = c->geo_conn;
+    a.geo.stride = (size_t)c->L.N[0] * c->L.N[1];
+    a.Pn = Pn;
+    a.PE = PE;
+    for (int d = 0; d < 3; ++d) {
+        a.F[d] = c->F[d];
+        a.E[d] = c->E[d];
+    }
+    a.rhs = c->rhs;
+    a.coef = c->coef;
+    a.dtp = dtp;
+    a.floors = c->cfg.floors;
+    a.rho_fl = c->cfg.rho_floor;
+    a.u_fl = c->cfg.u_floor;
+    return a;
+}
+
+NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
+{
+    NewtonArgs a{};
+    a.s = s;
+    a.tol = c->cfg.tol;
+    a.eps = c->cfg.eps_fd;
+    a.eps_bt = c->cfg.eps_bt;
+    a.k_max = c->cfg.k_max;
+    a.ls_max = c->cfg.ls_max;
+    a.iters = c->iters;
+    a.resid = c->resid;
+    a.flags = c->flags;
+    a.stats = c->stats;
+    return a;
+}
+
+// Event bracket around a launch group when kernel timing is on.
+struct Timed {
+    grim_ctx* c;
+    int group;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(grim_ctx* c_, int g, hipStream_t s) : c(c_), group(g), st(s)
+    {
+        if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            hipEventRecord(a, st);
+    }
+    ~Timed()
+    {
+        if (a && b) {
+            hipEventRecord(b, st);
+            c->marks.push_back({group, a, b});
+        }
+    }
+};
+
+// One stage: flux stage on PE (ghosts of PE must be filled), then Newton.
+int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, int stage, hipStream_t st)
+{
+    StageArgs s = stage_args(c, Pn, PE, dtp);
+    if (c->timing) {
+        {
+            Timed t(c, 1, st);
+            HIP_TRY(c, grim::launch_fluxes(s, c->nvar, c->cfg.metric, st));
+        }
+        if (c->cfg.ndim >= 2) {
+            Timed t(c, 2, st);
+            HIP_TRY(c, grim::launch_emf(s, st));
+        }
+        {
+            Timed t(c, 3, st);
+            HIP_TRY(c, grim::launch_rhs(s, c->nvar, c->cfg.metric, st));
+        }
+    } else {
+        HIP_TRY(c, grim::launch_explicit_stage(s, c->nvar, c->cfg.metric, st));
+    }
+    NewtonArgs n = newton_args(c, s);
+    n.out = out;
+    n.out_ghosted = 1;
+    n.stage = stage;
+    Timed t(c, 4, st);
+    HIP_TRY(c, grim::launch_newton(n, c->nvar, c->cfg.metric, c->cfg.jac_precision, st));
+    return GRIM_OK;
+}
+
+// One full step from buffer `from` into the other buffer, enqueued on st.
+int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st)
+{
+    double* A = c->P[from];
+    double* B = c->P[1 - from];
+    const int bc[3] = {c->cfg.bc[0], c->cfg.bc[1], c->cfg.bc[2]};
+    {
+        Timed t(c, 0, st);
+        HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, A, st));
+    }
+    int rc = enqueue_stage(c, A, A, 0.5 * dt, B, 0, st);
+    if (rc) return rc;
+    {
+        Timed t(c, 0, st);
+        HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, B, st));
+    }
+    // stage 2 writes P_{n+1} over P^E = P_{n+1/2}: each lane reads its own
+    // zone of P^E before writing it, and nothing else reads P^E then.
+    return enqueue_stage(c, A, B, dt, B, 1, st);
+}
+
+int ensure_hook_buffers(grim_ctx* c)
+{
+    for (int i = 0; i < 2; ++i)
+        if (!c->hookP[i]) {
+            int rc = dalloc(c, &c->hookP[i], (size_t)c->nvar * c->L.cells);
+            if (rc) return rc;
+            HIP_TRY(c, hipMemsetAsync(c->hookP[i], 0, sizeof(double) * c->nvar * c->L.cells, c->st));
+        }
+    return GRIM_OK;
+}
+
+// Stage the hook inputs P_n (interior) and P^E (interior) into ghosted
+// buffers and run the explicit stage.
+int hook_setup(grim_ctx* c, const double* Pn, const double* PE, double dtp, StageArgs* out, double* dbg_divF,
+               double* dbg_src, double* dbg_sp)
+{
+    if (!Pn || !PE) return fail(c, GRIM_E_INVALID_ARG, "null input pointer");
+    if (!(dtp > 0.0) || !std::isfinite(dtp)) return fail(c, GRIM_E_INVALID_ARG, "dt' must be positive");
+    int rc = ensure_hook_buffers(c);
+    if (rc) return rc;
+    HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, Pn, 0, c->hookP[0], 1, c->st));
+    HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, PE, 0, c->hookP[1], 1, c->st));
+    const int bc[3] = {c->cfg.bc[0], c->cfg.bc[1], c->cfg.bc[2]};
+    HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, c->hookP[1], c->st));
+    StageArgs s = stage_args(c, c->hookP[0], c->hookP[1], dtp);
+    s.dbg_divF = dbg_divF;
+    s.dbg_src = dbg_src;
+    s.dbg_sp = dbg_sp;
+    HIP_TRY(c, grim::launch_explicit_stage(s, c->nvar, c->cfg.metric, c->st));
+    *out = s;
+    return GRIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grim_last_global_error(void) { return g_last_error.c_str(); }
+
+const char* grim_last_error(const grim_ctx_t* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+size_t grim_device_bytes(const grim_ctx_t* ctx) { return ctx ? ctx->bytes : 0; }
+
+int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
+{
+    if (!cfg || !out) return fail(nullptr, GRIM_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    std::string why;
+    if (validate(cfg, why)) return fail(nullptr, GRIM_E_INVALID_ARG, "invalid config: " + why);
+    grim_ctx* c = new (std::nothrow) grim_ctx();
+    if (!c) return fail(nullptr, GRIM_E_OOM, "host allocation failed");
+    c->cfg = *cfg;
+    c->st = (hipStream_t)hip_stream;
+    {
+        // NULL: an owned blocking stream (it orders itself with the legacy
+        // default stream, which PyTorch uses by default).  Graphs are
+        // captured on a private non-blocking stream and replayed on st.
+        hipError_t e = hipSuccess;
+        if (!c->st) {
+            e = hipStreamCreateWithFlags(&c->st, hipStreamDefault);
+            c->own_st = e == hipSuccess;
+        }
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_last_error = std::string("stream creation: ") + hipGetErrorString(e);
+            release(c);
+            delete c;
+            return GRIM_E_HIP;
+        }
+    }
+    c->nvar = cfg->model;
+    Layout& L = c->L;
+    L.ndim = cfg->ndim;
+    const int n[3] = {cfg->n1, cfg->n2, cfg->n3};
+    for (int d = 0; d < 3; ++d) {
+        L.n[d] = n[d];
+        L.g[d] = d < cfg->ndim ? cfg->ng : 0;
+        L.N[d] = n[d] + 2 * L.g[d];
+        L.xs[d] = cfg->x_start[d];
+        L.dx[d] = d < cfg->ndim ? (cfg->x_end[d] - cfg->x_start[d]) / n[d] : 1.0;
+    }
+    L.cells = (long)L.N[0] * L.N[1] * L.N[2];
+    L.nz = (long)n[0] * n[1] * n[2];
+    Phys& ph = c->ph;
+    ph.gam = cfg->gamma;
+    ph.gm1 = cfg->gamma - 1.0;
+    ph.tau = cfg->tau_R;
+    ph.chi = cfg->chi;
+    ph.nu = cfg->nu;
+    ph.theta = cfg->plm_theta;
+    if (cfg->model == GRIM_EMHD) {
+        ph.kq = std::sqrt(cfg->tau_R / cfg->chi);
+        ph.kd = std::sqrt(cfg->tau_R / cfg->nu);
+        ph.vq2 = (cfg->gamma - 1.0) * cfg->chi / cfg->tau_R;
+        ph.vd2 = 4.0 * cfg->nu / (3.0 * cfg->tau_R);
+    }
+    const size_t nv = (size_t)c->nvar;
+    int rc = GRIM_OK;
+    for (int i = 0; i < 2 && !rc; ++i) rc = dalloc(c, &c->P[i], nv * L.cells);
+    for (int d = 0; d < cfg->ndim && !rc; ++d) rc = dalloc(c, &c->F[d], nv * L.cells);
+    if (cfg->ndim >= 2)
+        for (int d = 0; d < 3 && !rc; ++d)
+            if (cfg->ndim == 3 || d == 2) rc = dalloc(c, &c->E[d], (size_t)L.cells);
+    if (!rc) rc = dalloc(c, &c->rhs, nv * L.nz);
+    if (!rc && c->nvar == GRIM_EMHD) rc = dalloc(c, &c->coef, (size_t)grim::kEmhdCoef * L.nz);
+    if (!rc) rc = dalloc(c, &c->interior, nv * L.nz);
+    if (!rc) rc = dalloc(c, &c->iters, (size_t)L.nz);
+    if (!rc) rc = dalloc(c, &c->resid, (size_t)L.nz);
+    if (!rc) rc = dalloc(c, &c->flags, (size_t)L.nz);
+    if (!rc) rc = dalloc(c, &c->stats, 1);
+    if (!rc) rc = dalloc(c, &c->u64, 4);
+    if (!rc && cfg->metric == GRIM_MKS_KERR) {
+        const size_t s = (size_t)L.N[0] * L.N[1];
+        rc = dalloc(c, &c->geo_centre, grim::kGeoDoubles * s);
+        for (int d = 0; d < 3 && !rc; ++d) rc = dalloc(c, &c->geo_face[d], grim::kGeoDoubles * s);
+        if (!rc) rc = dalloc(c, &c->geo_conn, 64 * s);
+    }
+    if (rc) {
+        g_last_error = c->err;
+        release(c);
+        delete c;
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMemsetAsync(c->P[i], 0, sizeof(double) * nv * L.cells, c->st);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+        if (c->F[d]) e = hipMemsetAsync(c->F[d], 0, sizeof(double) * nv * L.cells, c->st);
+        if (e == hipSuccess && c->E[d]) e = hipMemsetAsync(c->E[d], 0, sizeof(double) * L.cells, c->st);
+    }
+    if (e == hipSuccess && cfg->metric == GRIM_MKS_KERR)
+        e = grim::build_geometry(L, cfg->spin_a, cfg->mks_h, c->geo_centre, c->geo_face, c->geo_conn, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        g_last_error = std::string("device initialisation: ") + hipGetErrorString(e);
+        release(c);
+        delete c;
+        return GRIM_E_HIP;
+    }
+    *out = c;
+    return GRIM_OK;
+}
+
+int grim_destroy(grim_ctx_t* ctx)
+{
+    if (!ctx) return GRIM_OK;
+    hipStreamSynchronize(ctx->st);
+    release(ctx);
+    delete ctx;
+    return GRIM_OK;
+}
+
+int grim_set_prims(grim_ctx_t* c, const double* P, int on_device)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!P) return fail(c, GRIM_E_INVALID_ARG, "null P");
+    const size_t bytes = sizeof(double) * c->nvar * c->L.nz;
+    const double* src = P;
+    if (!on_device) {
+        HIP_TRY(c, hipMemcpyAsync(c->interior, P, bytes, hipMemcpyHostToDevice, c->st));
+        src = c->interior;
+    }
+    HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, src, 0, c->P[c->cur], 1, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_get_prims(grim_ctx_t* c, double* P, int on_device)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!P) return fail(c, GRIM_E_INVALID_ARG, "null P");
+    const size_t bytes = sizeof(double) * c->nvar * c->L.nz;
+    if (on_device) {
+        HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, c->P[c->cur], 1, P, 0, c->st));
+    } else {
+        HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, c->P[c->cur], 1, c->interior, 0, c->st));
+        HIP_TRY(c, hipMemcpyAsync(P, c->interior, bytes, hipMemcpyDeviceToHost, c->st));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_cfl_dt(grim_ctx_t* c, double cfl, double* dt)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!dt || !(cfl > 0.0)) return fail(c, GRIM_E_INVALID_ARG, "cfl must be positive and dt non-null");
+    const unsigned long long init = 0x7FEFFFFFFFFFFFFFull;  // largest finite double
+    HIP_TRY(c, hipMemcpyAsync(c->u64, &init, sizeof(init), hipMemcpyHostToDevice, c->st));
+    grim::GeoTables geo{c->geo_centre, {c->geo_face[0], c->geo_face[1], c->geo_face[2]}, c->geo_conn,
+                        (size_t)c->L.N[0] * c->L.N[1]};
+    HIP_TRY(c, grim::launch_cfl(c->L, c->ph, geo, c->nvar, c->cfg.metric, c->P[c->cur], c->u64, c->st));
+    unsigned long long bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->u64, sizeof(bits), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    double m;
+    std::memcpy(&m, &bits, sizeof(m));
+    if (!std::isfinite(m) || !(m > 0.0)) return fail(c, GRIM_E_STATE, "non-finite or zero time step (bad state?)");
+    *dt = cfl * m;
+    return GRIM_OK;
+}
+
+int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* stats)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return fail(c, GRIM_E_INVALID_ARG, "bad dt or nsteps");
+    HIP_TRY(c, grim::launch_zero_stats(c->stats, c->st));
+    if (use_graph && nsteps > 0 && !c->timing) {
+        if (c->graph_dt != dt || !c->graph[0]) {
+            for (int i = 0; i < 2; ++i)
+                if (c->graph[i]) {
+                    hipGraphExecDestroy(c->graph[i]);
+                    c->graph[i] = nullptr;
+                }
+            for (int i = 0; i < 2; ++i) {
+                hipGraph_t g = nullptr;
+                HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+                int rc = enqueue_step(c, i, dt, c->cap);
+                hipError_t e = hipStreamEndCapture(c->cap, &g);
+                if (rc) {
+                    if (g) hipGraphDestroy(g);
+                    return rc;
+                }
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&c->graph[i], g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+            }
+            c->graph_dt = dt;
+        }
+        for (int s = 0; s < nsteps; ++s) {
+            HIP_TRY(c, hipGraphLaunch(c->graph[c->cur], c->st));
+            c->cur = 1 - c->cur;
+        }
+    } else {
+        for (int s = 0; s < nsteps; ++s) {
+            int rc = enqueue_step(c, c->cur, dt, c->st);
+            if (rc) return rc;
+            c->cur = 1 - c->cur;
+        }
+    }
+    if (stats) {
+        DevStats d{};
+        HIP_TRY(c, hipMemcpyAsync(&d, c->stats, sizeof(d), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+        const double per_stage = (double)c->L.nz * (double)(nsteps > 0 ? nsteps : 1);
+        stats->mean_iters[0] = (double)d.iters[0] / per_stage;
+        stats->mean_iters[1] = (double)d.iters[1] / per_stage;
+        stats->max_iters = (int32_t)d.max_iters;
+        stats->pad = 0;
+        stats->n_fail = (int64_t)d.n_fail;
+        stats->n_ls_exhausted = (int64_t)d.n_ls;
+        stats->n_unphysical = (int64_t)d.n_unphys;
+        double mr;
+        std::memcpy(&mr, &d.max_resid_bits, sizeof(mr));
+        stats->max_resid = mr;
+        stats->zone_stages = (int64_t)d.zone_stages;
+        stats->n_resid_calls = (int64_t)d.resid_calls;
+    }
+    return GRIM_OK;
+}
+
+int grim_residual(grim_ctx_t* c, const double* Pn, const double* PE, double dtp, const double* P, double* R,
+                  double* rnorm)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!P || !R) return fail(c, GRIM_E_INVALID_ARG, "null P or R");
+    StageArgs s;
+    int rc = hook_setup(c, Pn, PE, dtp, &s, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    HIP_TRY(c, grim::launch_residual(s, c->nvar, c->cfg.metric, P, R, rnorm, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_stage_solve(grim_ctx_t* c, const double* Pn, const double* PE, double dtp, const double* guess,
+                     double* P_out, int32_t* iters, double* resid, uint8_t* flags)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!P_out) return fail(c, GRIM_E_INVALID_ARG, "null P_out");
+    StageArgs s;
+    int rc = hook_setup(c, Pn, PE, dtp, &s, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    HIP_TRY(c, grim::launch_zero_stats(c->stats, c->st));
+    NewtonArgs n = newton_args(c, s);
+    n.guess = guess;
+    n.out = P_out;
+    n.out_ghosted = 0;
+    n.stage = 0;
+    if (iters) n.iters = iters;
+    if (resid) n.resid = resid;
+    if (flags) n.flags = flags;
+    HIP_TRY(c, grim::launch_newton(n, c->nvar, c->cfg.metric, c->cfg.jac_precision, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_explicit(grim_ctx_t* c, const double* PE, double* divF, double* srcE, double* emhd_sp)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!divF || !srcE) return fail(c, GRIM_E_INVALID_ARG, "null divF or srcE");
+    StageArgs s;
+    int rc = hook_setup(c, PE, PE, 1.0, &s, divF, srcE, emhd_sp);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_get_zone_results(grim_ctx_t* c, uint8_t* flags, int32_t* iters, int on_device)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (flags) HIP_TRY(c, hipMemcpyAsync(flags, c->flags, (size_t)c->L.nz, k, c->st));
+    if (iters) HIP_TRY(c, hipMemcpyAsync(iters, c->iters, sizeof(int32_t) * c->L.nz, k, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_profile(grim_ctx_t* c, int enable)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    c->timing = enable != 0;
+    return GRIM_OK;
+}
+
+int grim_kernel_times(grim_ctx_t* c, double* ms, int64_t* launches, int n)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!ms || !launches || n < 5) return fail(c, GRIM_E_INVALID_ARG, "need 5-entry output arrays");
+    for (int i = 0; i < n; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    for (auto& m : c->marks) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) {
+            ms[m.group] += t;
+            launches[m.group] += 1;
+        }
+        hipEventDestroy(m.a);
+        hipEventDestroy(m.b);
+    }
+    c->marks.clear();
+    return GRIM_OK;
+}
+
+int grim_stream_add(grim_ctx_t* c, const double* a, const double* b, double* cc, size_t n)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!a || !b || !cc) return fail(c, GRIM_E_INVALID_ARG, "null pointer");
+    HIP_TRY(c, grim::launch_stream_add(a, b, cc, n, c->st));
+    return GRIM_OK;
+}
+
+}  // extern "C"

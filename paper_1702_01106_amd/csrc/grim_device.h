@@ -1,0 +1,285 @@
+// Device-side physics of the grim method for gfx950: metric access, derived
+// fluid quantities, conserved variables, fluxes and wave speeds.  Everything
+// here is __forceinline__ register code; the kernels that use it live in
+// kernels.hip and newton.hip.
+//
+// Metric access is templated on a geometry type.  Each type declares at
+// compile time which entries of g_{mu nu} and g^{mu nu} are structurally
+// nonzero (nzc / nzn), so that after unrolling the Minkowski path carries no
+// metric arithmetic at all and the Kerr-Schild path skips the theta-decoupled
+// zeros (g_{0 2} = g_{1 2} = g_{2 3} = 0).  IEEE rules forbid the compiler
+// from folding 0*x or 0+x itself, so the sparsity is made explicit here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace grim {
+
+enum : int { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7, QQ = 8, DP = 9 };
+
+// Packed index of a symmetric 4x4 entry (m, n).
+__host__ __device__ constexpr int sidx(int m, int n)
+{
+    return m <= n ? m * 4 - m * (m - 1) / 2 + n - m : n * 4 - n * (n - 1) / 2 + m - n;
+}
+
+// Physical constants shared by every kernel of one context.
+struct Phys {
+    double gam;      // adiabatic index
+    double gm1;      // gamma - 1
+    double kq, kd;   // sqrt(tau_R/chi), sqrt(tau_R/nu): EMHD rescaling (eqs. q, dP)
+    double vq2, vd2; // (gamma-1) chi/tau_R, 4 nu/(3 tau_R) (Sec. 4.1)
+    double tau, chi, nu;
+    double theta;    // generalized-minmod parameter
+};
+
+// ---------------------------------------------------------------- geometry
+
+// Flat space in Cartesian coordinates.
+struct GeoMink {
+    static constexpr bool kFlat = true;
+    __device__ __forceinline__ static constexpr bool nzc(int m, int n) { return m == n; }
+    __device__ __forceinline__ static constexpr bool nzn(int m, int n) { return m == n; }
+    __device__ __forceinline__ constexpr double gcov(int m, int n) const { return m == 0 && n == 0 ? -1.0 : 1.0; }
+    __device__ __forceinline__ constexpr double gcon(int m, int n) const { return m == 0 && n == 0 ? -1.0 : 1.0; }
+    __device__ __forceinline__ constexpr double gdet() const { return 1.0; }
+    __device__ __forceinline__ constexpr double alpha() const { return 1.0; }
+};
+
+// Kerr in modified Kerr-Schild coordinates: stationary, axisymmetric, with
+// X2 decoupled from the other coordinates.  Seven nonzero entries each for
+// g_{mu nu} and g^{mu nu}: (0,0) (0,1) (0,3) (1,1) (1,3) (2,2) (3,3).
+struct GeoKS {
+    static constexpr bool kFlat = false;
+    double c[7];  // g_{mu nu}
+    double u[7];  // g^{mu nu}
+    double gd, al;
+    __device__ __forceinline__ static constexpr bool nzc(int m, int n)
+    {
+        return !((m == 2) ^ (n == 2));
+    }
+    __device__ __forceinline__ static constexpr bool nzn(int m, int n) { return nzc(m, n); }
+    __device__ __forceinline__ static constexpr int k7(int m, int n)
+    {
+        // (0,0)->0 (0,1)->1 (0,3)->2 (1,1)->3 (1,3)->4 (2,2)->5 (3,3)->6
+        return (m > n) ? k7(n, m)
+                       : (m == 0 ? (n == 0 ? 0 : (n == 1 ? 1 : 2))
+                                 : (m == 1 ? (n == 1 ? 3 : 4) : (m == 2 ? 5 : 6)));
+    }
+    __device__ __forceinline__ double gcov(int m, int n) const { return c[k7(m, n)]; }
+    __device__ __forceinline__ double gcon(int m, int n) const { return u[k7(m, n)]; }
+    __device__ __forceinline__ double gdet() const { return gd; }
+    __device__ __forceinline__ double alpha() const { return al; }
+};
+
+// Number of doubles per point in a Kerr-Schild metric table: 7 + 7 + gdet + alpha.
+constexpr int kGeoDoubles = 16;
+
+// Load the metric of table point p from an SoA table [kGeoDoubles][stride].
+__device__ __forceinline__ void load_geo(GeoKS& g, const double* __restrict__ t, size_t p, size_t stride)
+{
+#pragma unroll
+    for (int q = 0; q < 7; ++q) g.c[q] = t[q * stride + p];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) g.u[q] = t[(7 + q) * stride + p];
+    g.gd = t[14 * stride + p];
+    g.al = t[15 * stride + p];
+}
+
+// dn_m = g_{m n} up^n, structural zeros skipped.
+template <class G>
+__device__ __forceinline__ void lower(const G& g, const double* up, double* dn)
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double acc = 0.0;
+        bool first = true;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            if (G::nzc(m, n)) {
+                const double t = g.gcov(m, n) * up[n];
+                acc = first ? t : acc + t;
+                first = false;
+            }
+        }
+        dn[m] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- fluid state
+
+template <int NV>
+struct St {
+    double ucon[4], ucov[4], bcon[4], bcov[4];
+    double bsq, pg;
+    double bh[4], bhc[4];  // unit b (EMHD only)
+};
+
+// Derived quantities of primitive state P (Sec. 4): gamma = sqrt(1 + g_ij
+// ut^i ut^j), u^0 = gamma/alpha, u^i = ut^i - gamma alpha g^{0i};
+// b^0 = B^i u_i, b^i = (B^i + b^0 u^i)/u^0; P = (gamma-1) u; bhat = b/|b|
+// (zero for b^2 < 1e-30).
+template <int NV, class G>
+__device__ __forceinline__ void derive(const double* P, const G& g, const Phys& ph, St<NV>& s)
+{
+    double q2 = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+#pragma unroll
+        for (int j = 1; j < 4; ++j)
+            if (G::nzc(i, j)) {
+                const double t = g.gcov(i, j) * P[1 + i] * P[1 + j];
+                q2 = first ? t : q2 + t;
+                first = false;
+            }
+    const double gl = sqrt(1.0 + q2);
+    if constexpr (G::kFlat) {
+        s.ucon[0] = gl;
+#pragma unroll
+        for (int i = 1; i < 4; ++i) s.ucon[i] = P[1 + i];
+    } else {
+        s.ucon[0] = gl / g.alpha();
+        const double ga = gl * g.alpha();
+#pragma unroll
+        for (int i = 1; i < 4; ++i) s.ucon[i] = P[1 + i] - ga * g.gcon(0, i);
+    }
+    lower(g, s.ucon, s.ucov);
+    const double b0 = P[B1] * s.ucov[1] + P[B2] * s.ucov[2] + P[B3] * s.ucov[3];
+    const double iu0 = 1.0 / s.ucon[0];
+    s.bcon[0] = b0;
+#pragma unroll
+    for (int i = 1; i < 4; ++i) s.bcon[i] = (P[B1 + i - 1] + b0 * s.ucon[i]) * iu0;
+    lower(g, s.bcon, s.bcov);
+    s.bsq = s.bcon[0] * s.bcov[0] + s.bcon[1] * s.bcov[1] + s.bcon[2] * s.bcov[2] + s.bcon[3] * s.bcov[3];
+    s.pg = ph.gm1 * P[UU];
+    if constexpr (NV == 10) {
+        const bool has = s.bsq > 1e-30;
+        const double ib = has ? 1.0 / sqrt(s.bsq) : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            s.bh[m] = s.bcon[m] * ib;
+            s.bhc[m] = s.bcov[m] * ib;
+        }
+    }
+}
+
+// Row DIR of the mixed stress tensor T^DIR_nu (eq. fullSEtens), for nu = 0..3:
+// (rho + u + P + b^2) u^DIR u_nu + (P + b^2/2) delta^DIR_nu - b^DIR b_nu
+//  + q (bhat^DIR u_nu + u^DIR bhat_nu) - DP (bhat^DIR bhat_nu - (delta^DIR_nu + u^DIR u_nu)/3)
+template <int NV, int DIR>
+__device__ __forceinline__ void trow(const double* P, const St<NV>& s, double* T)
+{
+    const double w = P[RHO] + P[UU] + s.pg + s.bsq;
+    const double pt = s.pg + 0.5 * s.bsq;
+    const double wu = w * s.ucon[DIR];
+    const double bd = s.bcon[DIR];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        double t = wu * s.ucov[n] - bd * s.bcov[n];
+        if (n == DIR) t += pt;
+        if constexpr (NV == 10) {
+            const double q = P[QQ], dp = P[DP];
+            double h = s.ucon[DIR] * s.ucov[n];
+            if (n == DIR) h += 1.0;
+            t += q * (s.bh[DIR] * s.ucov[n] + s.ucon[DIR] * s.bhc[n]);
+            t -= dp * (s.bh[DIR] * s.bhc[n] - h * (1.0 / 3.0));
+        }
+        T[n] = t;
+    }
+}
+
+// EMHD rescaled variables (eqs. q and dP): qt = q sqrt(tau/(chi rho Theta^2)),
+// DPt = DP sqrt(tau/(nu rho Theta)), Theta = P/rho; written as
+// qt = q sqrt(tau/chi) sqrt(rho)/P and DPt = DP sqrt(tau/nu)/sqrt(P).
+template <int NV>
+__device__ __forceinline__ void rescaled(const double* P, const St<NV>& s, const Phys& ph, double& qt, double& dpt)
+{
+    const double ip = 1.0 / s.pg;
+    qt = P[QQ] * ph.kq * sqrt(P[RHO]) * ip;
+    dpt = P[DP] * ph.kd * sqrt(ip);
+}
+
+// Conserved vector U (Sec. 4: sqrt(-g) times rho u^0, T^0_nu, B^i, qt u^0, DPt u^0).
+template <int NV, class G>
+__device__ __forceinline__ void conserved(const double* P, const G& g, const St<NV>& s, const Phys& ph, double* U)
+{
+    double T[4];
+    trow<NV, 0>(P, s, T);
+    const double gd = g.gdet();
+    U[RHO] = gd * P[RHO] * s.ucon[0];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) U[UU + n] = gd * T[n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[B1 + i] = gd * P[B1 + i];
+    if constexpr (NV == 10) {
+        double qt, dpt;
+        rescaled<NV>(P, s, ph, qt, dpt);
+        U[QQ] = gd * qt * s.ucon[0];
+        U[DP] = gd * dpt * s.ucon[0];
+    }
+}
+
+// Flux along DIR (1..3): sqrt(-g) times rho u^d, T^d_nu, b^i u^d - b^d u^i,
+// qt u^d, DPt u^d.  The induction flux takes the sign that follows from
+// d_mu(sqrt(-g) *F^{mu i}) = 0 with B^i = *F^{i t}.
+template <int NV, int DIR, class G>
+__device__ __forceinline__ void flux(const double* P, const G& g, const St<NV>& s, const Phys& ph, double* F)
+{
+    double T[4];
+    trow<NV, DIR>(P, s, T);
+    const double gd = g.gdet();
+    F[RHO] = gd * P[RHO] * s.ucon[DIR];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) F[UU + n] = gd * T[n];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) F[B1 + i - 1] = (i == DIR) ? 0.0 : gd * (s.bcon[i] * s.ucon[DIR] - s.bcon[DIR] * s.ucon[i]);
+    if constexpr (NV == 10) {
+        double qt, dpt;
+        rescaled<NV>(P, s, ph, qt, dpt);
+        F[QQ] = gd * qt * s.ucon[DIR];
+        F[DP] = gd * dpt * s.ucon[DIR];
+    }
+}
+
+// v_max^2 (Sec. 4.1, eq. modcs).
+template <int NV>
+__device__ __forceinline__ double vmax2(const double* P, const St<NV>& s, const Phys& ph)
+{
+    const double e = P[RHO] + ph.gam * P[UU];
+    const double cs2 = ph.gam * ph.gm1 * P[UU] / e;
+    const double va2 = s.bsq / (e + s.bsq);
+    double ct2 = cs2;
+    if constexpr (NV == 10) ct2 = 0.5 * (cs2 + ph.vq2 + sqrt(cs2 * cs2 + ph.vq2 * ph.vq2)) + ph.vd2;
+    return ct2 + va2 - ct2 * va2;
+}
+
+// Largest |grid-frame speed| along DIR of waves at +-v_max in the fluid frame:
+// the roots of (1-v^2)(u^d - l u^0)^2 - v^2 (g^00 l^2 - 2 g^0d l + g^dd) = 0;
+// max|root| = (|B| + sqrt(B^2 - 4AC)) / (2|A|).
+template <int NV, int DIR, class G>
+__device__ __forceinline__ double cmax(const double* P, const G& g, const St<NV>& s, const Phys& ph)
+{
+    const double v2 = vmax2<NV>(P, s, ph);
+    const double a = 1.0 - v2;
+    const double u0 = s.ucon[0], ud = s.ucon[DIR];
+    const double A = a * u0 * u0 - v2 * g.gcon(0, 0);
+    double B = a * u0 * ud;
+    if (G::nzn(0, DIR)) B -= v2 * g.gcon(0, DIR);
+    B *= -2.0;
+    const double C = a * ud * ud - v2 * g.gcon(DIR, DIR);
+    const double disc = fmax(B * B - 4.0 * A * C, 0.0);
+    return (fabs(B) + sqrt(disc)) / (2.0 * fabs(A));
+}
+
+// Generalized minmod slope minmod(theta a, (a+b)/2, theta b) (Sec. 2.3, 2.4.1).
+__device__ __forceinline__ double gmm(double a, double b, double th)
+{
+    const double x = th * a, y = 0.5 * (a + b), z = th * b;
+    const double mn = fmin(x, fmin(y, z)), mx = fmax(x, fmax(y, z));
+    return mn > 0.0 ? mn : (mx < 0.0 ? mx : 0.0);
+}
+
+}  // namespace grim

@@ -1,0 +1,103 @@
+// Internal declarations of libgrim: grid layout, kernel argument blocks and
+// the host-side launchers implemented in kernels.hip and newton.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "grim_device.h"
+
+namespace grim {
+
+// Ghosted structure-of-arrays grid: cell (i, j, k) of variable v sits at
+// v * cells + (k * N2 + j) * N1 + i, with interior cells i in [g1, g1 + n1).
+struct Layout {
+    int ndim;
+    int n[3];  // interior extents (1 for inactive directions)
+    int g[3];  // ghost offsets (0 for inactive directions)
+    int N[3];  // ghosted extents
+    long cells;
+    long nz;   // interior zones
+    double xs[3], dx[3];
+    __host__ __device__ long cell(int i, int j, int k) const { return ((long)k * N[1] + j) * N[0] + i; }
+    __host__ __device__ long stride(int d) const { return d == 0 ? 1L : (d == 1 ? (long)N[0] : (long)N[0] * N[1]); }
+};
+
+// Device-side accumulators of the solver statistics.
+struct DevStats {
+    unsigned long long iters[2];
+    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls;
+    unsigned long long max_resid_bits;
+    unsigned int max_iters;
+    unsigned int pad;
+};
+
+// Metric tables (Kerr-Schild only).  Centre and face tables depend on
+// (i, j) only: the metric is independent of X3.  Layout [kGeoDoubles][N2*N1];
+// the face table of direction d holds the metric at the low face of the
+// cell in direction d.  conn: Gamma^l_{m n} at centres, [64][N2*N1].
+struct GeoTables {
+    const double* centre;
+    const double* face[3];
+    const double* conn;
+    size_t stride;  // N1 * N2
+};
+
+// Per-zone EMHD coefficients frozen at P^E (count and order shared by the
+// rhs and Newton kernels).
+constexpr int kEmhdCoef = 13;  // bh[4], thn, u0n, cbun, aq1, aq2, aq3, ad2, ad3, chalf
+
+struct StageArgs {
+    Layout L;
+    Phys ph;
+    GeoTables geo;
+    const double* Pn;   // ghosted P_n
+    const double* PE;   // ghosted P^E (ghosts filled)
+    double* F[3];       // face fluxes per active direction, ghosted layout
+    double* E[3];       // edge EMFs E1, E2, E3 (flux-CT), ghosted layout
+    double* rhs;        // [nvar][nz]
+    double* coef;       // [kEmhdCoef][nz] (EMHD)
+    double dtp;
+    int floors;
+    double rho_fl, u_fl;
+    // optional outputs of the explicit stage (test hook), [nvar][nz] / [nz][3]
+    double* dbg_divF;
+    double* dbg_src;
+    double* dbg_sp;
+};
+
+struct NewtonArgs {
+    StageArgs s;
+    const double* guess;   // interior layout or null (then P_n)
+    double* out;           // output primitives
+    int out_ghosted;       // 1: out is a ghosted array, 0: interior layout
+    int32_t* iters;
+    double* resid;
+    uint8_t* flags;
+    DevStats* stats;
+    int stage;             // 0 or 1 (statistics slot)
+    double tol, eps, eps_bt;
+    int k_max, ls_max;
+};
+
+// launchers (return hipSuccess or the launch error)
+hipError_t launch_fill_ghosts(const Layout& L, int nvar, const int bc[3], double* P, hipStream_t st);
+hipError_t launch_explicit_stage(const StageArgs& a, int nvar, int metric, hipStream_t st);
+hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t st);
+hipError_t launch_emf(const StageArgs& a, hipStream_t st);
+hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st);
+hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st);
+hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const double* P, double* R, double* rnorm,
+                           hipStream_t st);
+hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int nvar, int metric, const double* P,
+                      unsigned long long* out_bits, hipStream_t st);
+hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
+hipError_t launch_stream_add(const double* a, const double* b, double* c, size_t n, hipStream_t st);
+hipError_t launch_copy_interior(const Layout& L, int nvar, const double* src, int src_ghosted, double* dst,
+                                int dst_ghosted, hipStream_t st);
+hipError_t build_geometry(const Layout& L, double spin, double h, double* centre, double* face[3], double* conn,
+                          hipStream_t st);
+
+}  // namespace grim

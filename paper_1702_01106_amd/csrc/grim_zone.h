@@ -1,0 +1,104 @@
+// Per-zone data of one stage solve and the stage residual R(P) (Sec. 3,
+// eq. half_step_residual), evaluated in registers.  Shared by the Newton
+// kernel and the residual test hook.
+//
+// Every term of R that does not depend on the unknown P is folded by the
+// rhs kernel into rhs[v] (and, for EMHD, into the coefficient bundle), so
+// one residual evaluation is: derive the state of P, build U(P), and for
+// EMHD add the implicit relaxation terms:
+//   R_v  = U_v(P)/dt' - rhs_v
+//   R_q  += chalf qt(P) - aq1 (Theta - Theta_n) - aq2 (bhat.u - bhat.u_n) - aq3 (u^0 - u^0_n)
+//   R_DP += chalf DPt(P) - ad2 (bhat.u - bhat.u_n) - ad3 (u^0 - u^0_n)
+// where bhat.u = bhat_E^mu u_mu(P): the IMEX split of Sec. 2.3 with the
+// time derivatives of Theta, u_mu and u^0 differenced against P_n and every
+// coefficient frozen at P^E.
+#pragma once
+
+#include "grim_device.h"
+#include "grim_internal.h"
+
+namespace grim {
+
+template <int NV, class G>
+struct ZoneC {
+    G g;
+    double rhs[NV];
+    double idt;
+    double bh[4], thn, u0n, cbun, aq1, aq2, aq3, ad2, ad3, chalf;  // EMHD only
+};
+
+// Interior zone index z -> ghosted cell index.
+__device__ __forceinline__ long zone_cell(const Layout& L, long z)
+{
+    const int i = (int)(z % L.n[0]);
+    const long r = z / L.n[0];
+    const int j = (int)(r % L.n[1]);
+    const int k = (int)(r / L.n[1]);
+    return L.cell(i + L.g[0], j + L.g[1], k + L.g[2]);
+}
+
+template <int NV, class G>
+__device__ __forceinline__ void load_zone(const StageArgs& a, long z, long cell, ZoneC<NV, G>& zc)
+{
+    if constexpr (!G::kFlat) {
+        const long p = cell % ((long)a.L.N[0] * a.L.N[1]);
+        load_geo(zc.g, a.geo.centre, (size_t)p, a.geo.stride);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) zc.rhs[v] = a.rhs[(long)v * a.L.nz + z];
+    zc.idt = 1.0 / a.dtp;
+    if constexpr (NV == 10) {
+        const double* c = a.coef;
+        const long nz = a.L.nz;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) zc.bh[m] = c[m * nz + z];
+        zc.thn = c[4 * nz + z];
+        zc.u0n = c[5 * nz + z];
+        zc.cbun = c[6 * nz + z];
+        zc.aq1 = c[7 * nz + z];
+        zc.aq2 = c[8 * nz + z];
+        zc.aq3 = c[9 * nz + z];
+        zc.ad2 = c[10 * nz + z];
+        zc.ad3 = c[11 * nz + z];
+        zc.chalf = c[12 * nz + z];
+    }
+}
+
+template <int NV, class G>
+__device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G>& zc, const Phys& ph, double* R)
+{
+    St<NV> s;
+    derive<NV>(P, zc.g, ph, s);
+    double T[4];
+    trow<NV, 0>(P, s, T);
+    const double gd = zc.g.gdet();
+    const double gi = gd * zc.idt;
+    R[RHO] = gi * P[RHO] * s.ucon[0] - zc.rhs[RHO];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) R[UU + n] = gi * T[n] - zc.rhs[UU + n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) R[B1 + i] = gi * P[B1 + i] - zc.rhs[B1 + i];
+    if constexpr (NV == 10) {
+        double qt, dpt;
+        rescaled<NV>(P, s, ph, qt, dpt);
+        const double th = s.pg / P[RHO];
+        const double bu = zc.bh[0] * s.ucov[0] + zc.bh[1] * s.ucov[1] + zc.bh[2] * s.ucov[2] + zc.bh[3] * s.ucov[3];
+        const double dbu = bu - zc.cbun;
+        const double du0 = s.ucon[0] - zc.u0n;
+        R[QQ] = gi * qt * s.ucon[0] - zc.rhs[QQ] + zc.chalf * qt - zc.aq1 * (th - zc.thn) - zc.aq2 * dbu -
+                zc.aq3 * du0;
+        R[DP] = gi * dpt * s.ucon[0] - zc.rhs[DP] + zc.chalf * dpt - zc.ad2 * dbu - zc.ad3 * du0;
+    }
+}
+
+// sum of squares of a residual vector
+template <int NV>
+__device__ __forceinline__ double sumsq(const double* R)
+{
+    double s = R[0] * R[0];
+#pragma unroll
+    for (int v = 1; v < NV; ++v) s = fma(R[v], R[v], s);
+    return s;
+}
+
+}  // namespace grim

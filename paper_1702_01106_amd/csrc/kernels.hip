@@ -1,0 +1,578 @@
+// Explicit-stage kernels of libgrim for gfx950: ghost fill (a2), PLM + LLF
+// face fluxes (a3, a4), flux-CT edge EMFs (a5), the stage right-hand side
+// with explicit sources and the EMHD coefficient bundle (a6), the CFL time
+// step, the residual test hook, and small utility kernels.
+#include <hip/hip_runtime.h>
+
+#include "grim_internal.h"
+#include "grim_zone.h"
+
+namespace grim {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned nblocks(long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ ghosts
+
+// Every ghost cell takes its value from one interior cell: the per-direction
+// maps (periodic wrap, outflow clamp, polar mirror) are independent, so the
+// composite map equals filling X1, X2, X3 ghosts in turn.  Polar mirroring
+// negates utilde^2 and B^2.
+__global__ __launch_bounds__(kBlock) void k_fill_ghosts(Layout L, int nvar, int bc0, int bc1, int bc2, double* P)
+{
+    const long c = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= L.cells) return;
+    int idx[3];
+    idx[0] = (int)(c % L.N[0]);
+    idx[1] = (int)((c / L.N[0]) % L.N[1]);
+    idx[2] = (int)(c / ((long)L.N[0] * L.N[1]));
+    const int bc[3] = {bc0, bc1, bc2};
+    int src[3];
+    bool ghost = false, flip = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int p = idx[d], g = L.g[d], n = L.n[d];
+        if (d >= L.ndim || (p >= g && p < g + n)) {
+            src[d] = p;
+            continue;
+        }
+        ghost = true;
+        if (bc[d] == 0) {
+            src[d] = p < g ? p + n : p - n;
+        } else if (bc[d] == 1) {
+            src[d] = p < g ? g : g + n - 1;
+        } else {
+            src[d] = p < g ? 2 * g - 1 - p : 2 * (g + n) - 1 - p;
+            if (d == 1) flip = !flip;
+        }
+    }
+    if (!ghost) return;
+    const long s = L.cell(src[0], src[1], src[2]);
+    for (int v = 0; v < nvar; ++v) {
+        const double x = P[(long)v * L.cells + s];
+        P[(long)v * L.cells + c] = (flip && (v == U2 || v == B2)) ? -x : x;
+    }
+}
+
+// ------------------------------------------------------------------ fluxes
+
+// One thread per face on the low side of cell (i, j, k) in direction DIR.
+// Left/right states by generalized-minmod PLM of the four cells along DIR,
+// then LLF with c_max the largest |speed| of either state.
+template <int NV, class G, int DIR>
+__global__ __launch_bounds__(kBlock) void k_flux(StageArgs a, int lo0, int lo1, int lo2, int c0, int c1, int c2)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)c0 * c1 * c2) return;
+    const int i = lo0 + (int)(t % c0);
+    const int j = lo1 + (int)((t / c0) % c1);
+    const int k = lo2 + (int)(t / ((long)c0 * c1));
+    const Layout& L = a.L;
+    const long m = L.cell(i, j, k);
+    const long st = L.stride(DIR - 1);
+    const double th = a.ph.theta;
+    double PL[NV], PR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double* p = a.PE + (long)v * L.cells + m;
+        const double pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], pp1 = p[st];
+        PL[v] = pm1 + 0.5 * gmm(pm1 - pm2, p0 - pm1, th);
+        PR[v] = p0 - 0.5 * gmm(p0 - pm1, pp1 - p0, th);
+    }
+    G g;
+    if constexpr (!G::kFlat) load_geo(g, a.geo.face[DIR - 1], (size_t)((long)j * L.N[0] + i), a.geo.stride);
+    St<NV> sL, sR;
+    derive<NV>(PL, g, a.ph, sL);
+    derive<NV>(PR, g, a.ph, sR);
+    const double c = fmax(cmax<NV, DIR>(PL, g, sL, a.ph), cmax<NV, DIR>(PR, g, sR, a.ph));
+    double UL[NV], UR[NV], FL[NV], FR[NV];
+    conserved<NV>(PL, g, sL, a.ph, UL);
+    conserved<NV>(PR, g, sR, a.ph, UR);
+    flux<NV, DIR>(PL, g, sL, a.ph, FL);
+    flux<NV, DIR>(PR, g, sR, a.ph, FR);
+    double* F = a.F[DIR - 1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double f = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
+        F[(long)v * L.cells + m] = f;
+    }
+}
+
+// Flux-CT (Sec. 4.2): edge EMFs as the average of the four face B-fluxes
+// around each edge.  E3 on (i-1/2, j-1/2, k), E1 on (i, j-1/2, k-1/2), E2 on
+// (i-1/2, j, k-1/2); stored at cell (i, j, k).
+__global__ __launch_bounds__(kBlock) void k_emf(StageArgs a, int c0, int c1, int c2)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)c0 * c1 * c2) return;
+    const Layout& L = a.L;
+    const int g0 = L.g[0], g1 = L.g[1], g2 = L.g[2];
+    const int i = g0 + (int)(t % c0);
+    const int j = g1 + (int)((t / c0) % c1);
+    const int k = g2 + (int)(t / ((long)c0 * c1));
+    const long m = L.cell(i, j, k);
+    const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
+    const long C = L.cells;
+    const double* F1 = a.F[0];
+    const double* F2 = a.F[1];
+    const bool in0 = i < g0 + L.n[0], in1 = j < g1 + L.n[1];
+    if (L.ndim == 2) {
+        a.E[2][m] = 0.25 * (F1[B2 * C + m] + F1[B2 * C + m - s2] - F2[B1 * C + m] - F2[B1 * C + m - s1]);
+        return;
+    }
+    const double* F3 = a.F[2];
+    const bool in2 = k < g2 + L.n[2];
+    if (in2) a.E[2][m] = 0.25 * (F1[B2 * C + m] + F1[B2 * C + m - s2] - F2[B1 * C + m] - F2[B1 * C + m - s1]);
+    if (in0) a.E[0][m] = 0.25 * (F2[B3 * C + m] + F2[B3 * C + m - s3] - F3[B2 * C + m] - F3[B2 * C + m - s2]);
+    if (in1) a.E[1][m] = 0.25 * (F3[B1 * C + m] + F3[B1 * C + m - s1] - F1[B3 * C + m] - F1[B3 * C + m - s3]);
+}
+
+// ------------------------------------------------------------------ stage rhs
+
+// Generalized-minmod slope of the derived quantities used by the EMHD
+// sources: Theta, u_0..u_3, u^1..u^3 (8 values).
+template <int NV, class G>
+__device__ __forceinline__ void emhd_point(const double* P, const G& g, const Phys& ph, double* X)
+{
+    St<NV> s;
+    derive<NV>(P, g, ph, s);
+    X[0] = s.pg / P[RHO];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) X[1 + m] = s.ucov[m];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) X[4 + m] = s.ucon[m];
+}
+
+template <int NV>
+__device__ __forceinline__ void load_cell(const double* P, long cells, long m, double* out)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = P[(long)v * cells + m];
+}
+
+// One thread per interior zone:
+//   rhs_v = U_v(P_n)/dt' - divF_v(P^E) + S^E_v(P^E)
+// plus, for EMHD, every P-independent part of the relaxation sources folded
+// into rhs_q, rhs_DP, and the coefficients the Newton residual needs.
+template <int NV, class G>
+__global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
+{
+    const long z = (long)blockIdx.x * kBlock + threadIdx.x;
+    const Layout& L = a.L;
+    if (z >= L.nz) return;
+    const int ii = (int)(z % L.n[0]);
+    const int jj = (int)((z / L.n[0]) % L.n[1]);
+    const int kk = (int)(z / ((long)L.n[0] * L.n[1]));
+    const int i = ii + L.g[0], j = jj + L.g[1], k = kk + L.g[2];
+    const long m = L.cell(i, j, k);
+    const long C = L.cells;
+    const int nd = L.ndim;
+
+    // divergence of the face fluxes, B rows from the flux-CT EMFs
+    double divF[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+        for (int d = 0; d < nd; ++d) {
+            const long st = L.stride(d);
+            double fr, fl;
+            const bool ct = nd >= 2 && v >= B1 && v <= B3 && (nd == 3 || v != B3);
+            if (!ct) {
+                fr = a.F[d][(long)v * C + m + st];
+                fl = a.F[d][(long)v * C + m];
+            } else {
+                const int b = v - B1;
+                const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
+                // face B^b flux through faces normal to d, from the edge EMFs
+                auto face = [&](long c) -> double {
+                    if (b == d) return 0.0;
+                    if (d == 0 && b == 1) return 0.5 * (a.E[2][c] + a.E[2][c + s2]);
+                    if (d == 0 && b == 2) return -0.5 * (a.E[1][c] + a.E[1][c + s3]);
+                    if (d == 1 && b == 0) return -0.5 * (a.E[2][c] + a.E[2][c + s1]);
+                    if (d == 1 && b == 2) return 0.5 * (a.E[0][c] + a.E[0][c + s3]);
+                    if (d == 2 && b == 0) return 0.5 * (a.E[1][c] + a.E[1][c + s1]);
+                    return -0.5 * (a.E[0][c] + a.E[0][c + s2]);  // d == 2 && b == 1
+                };
+                fr = face(m + st);
+                fl = face(m);
+            }
+            s += (fr - fl) / L.dx[d];
+        }
+        divF[v] = s;
+    }
+
+    G g;
+    if constexpr (!G::kFlat) load_geo(g, a.geo.centre, (size_t)((long)j * L.N[0] + i), a.geo.stride);
+    const double idt = 1.0 / a.dtp;
+    double Pn[NV], PE[NV];
+    load_cell<NV>(a.Pn, C, m, Pn);
+    load_cell<NV>(a.PE, C, m, PE);
+    St<NV> sn, sE;
+    derive<NV>(Pn, g, a.ph, sn);
+    derive<NV>(PE, g, a.ph, sE);
+    double Un[NV];
+    conserved<NV>(Pn, g, sn, a.ph, Un);
+
+    // explicit geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E
+    double src[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) src[v] = 0.0;
+    double conn[4][4][4];
+    if constexpr (!G::kFlat) {
+        const size_t p = (size_t)((long)j * L.N[0] + i);
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) conn[l][q / 4][q % 4] = a.geo.conn[(size_t)(l * 16 + q) * a.geo.stride + p];
+        double T[4][4];
+        trow<NV, 0>(PE, sE, T[0]);
+        trow<NV, 1>(PE, sE, T[1]);
+        trow<NV, 2>(PE, sE, T[2]);
+        trow<NV, 3>(PE, sE, T[3]);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            double s = 0.0;
+#pragma unroll
+            for (int kap = 0; kap < 4; ++kap)
+#pragma unroll
+                for (int lam = 0; lam < 4; ++lam) s += T[kap][lam] * conn[lam][n][kap];
+            src[UU + n] = g.gdet() * s;
+        }
+    }
+
+    double rhs[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rhs[v] = Un[v] * idt - divF[v] + src[v];
+
+    double sq = 0.0, sdiv = 0.0, sdp = 0.0;
+    if constexpr (NV == 10) {
+        // limited slopes of Theta, u_mu, u^i of P^E (Sec. 2.3)
+        double X0[8];
+        emhd_point<NV>(PE, g, a.ph, X0);
+        double dX[3][8];
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dX[d][q] = 0.0;
+        for (int d = 0; d < nd; ++d) {
+            const long st = L.stride(d);
+            double Pm[NV], Pp[NV], Xm[8], Xp[8];
+            load_cell<NV>(a.PE, C, m - st, Pm);
+            load_cell<NV>(a.PE, C, m + st, Pp);
+            G gm, gp;
+            if constexpr (!G::kFlat) {
+                const int im = d == 0 ? i - 1 : i, jm = d == 1 ? j - 1 : j;
+                const int ip = d == 0 ? i + 1 : i, jp = d == 1 ? j + 1 : j;
+                load_geo(gm, a.geo.centre, (size_t)((long)jm * L.N[0] + im), a.geo.stride);
+                load_geo(gp, a.geo.centre, (size_t)((long)jp * L.N[0] + ip), a.geo.stride);
+            }
+            emhd_point<NV>(Pm, gm, a.ph, Xm);
+            emhd_point<NV>(Pp, gp, a.ph, Xp);
+            const double idx = 1.0 / L.dx[d];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dX[d][q] = gmm(X0[q] - Xm[q], Xp[q] - X0[q], a.ph.theta) * idx;
+        }
+        const double theta = X0[0];
+        double a1 = 0.0, a2 = 0.0, b1 = 0.0, divs = 0.0;
+        for (int d = 0; d < nd; ++d) {
+            a1 += sE.bh[d + 1] * dX[d][0];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                a2 += sE.bh[mu] * sE.ucon[d + 1] * dX[d][1 + mu];
+                b1 += sE.bh[d + 1] * sE.bh[mu] * dX[d][1 + mu];
+            }
+            divs += dX[d][4 + d + 1];
+        }
+        double ga = 0.0, gb = 0.0, gdv = 0.0;
+        if constexpr (!G::kFlat) {
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        ga += sE.bh[mu] * conn[l][n][mu] * sE.ucon[n] * sE.ucov[l];
+                        gb += sE.bh[mu] * sE.bh[n] * conn[l][mu][n] * sE.ucov[l];
+                    }
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) gdv += conn[mu][mu][l] * sE.ucon[l];
+        }
+        sq = a1 + theta * (a2 - ga);
+        sdiv = divs + gdv;
+        sdp = b1 - gb;
+
+        // fold the P-independent parts of the relaxation sources
+        const Phys& ph = a.ph;
+        const double gd = g.gdet();
+        const double tau = ph.tau;
+        const double rhoE = PE[RHO], thE = sE.pg / PE[RHO], u0E = sE.ucon[0];
+        double qtE, dptE, qtn, dptn;
+        rescaled<NV>(PE, sE, ph, qtE, dptE);
+        rescaled<NV>(Pn, sn, ph, qtn, dptn);
+        const double kqE = sqrt(tau / (ph.chi * rhoE * thE * thE));
+        const double kdE = sqrt(tau / (ph.nu * rhoE * thE));
+        const double cq = (kqE / tau) * (-rhoE * ph.chi);
+        const double cd = (kdE / tau) * (3.0 * rhoE * ph.nu);
+        const double thn = sn.pg / Pn[RHO];
+        const double u0n = sn.ucon[0];
+        const double cbun = sE.bh[0] * sn.ucov[0] + sE.bh[1] * sn.ucov[1] + sE.bh[2] * sn.ucov[2] + sE.bh[3] * sn.ucov[3];
+        rhs[QQ] += gd * (-qtn / (2.0 * tau) + cq * sq + 0.5 * qtE * sdiv);
+        rhs[DP] += gd * (-dptn / (2.0 * tau) + cd * (sdp - sdiv / 3.0) + 0.5 * dptE * sdiv);
+        double* co = a.coef;
+        const long nz = L.nz;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) co[mu * nz + z] = sE.bh[mu];
+        co[4 * nz + z] = thn;
+        co[5 * nz + z] = u0n;
+        co[6 * nz + z] = cbun;
+        co[7 * nz + z] = gd * cq * sE.bh[0] * idt;
+        co[8 * nz + z] = gd * cq * thE * u0E * idt;
+        co[9 * nz + z] = gd * 0.5 * qtE * idt;
+        co[10 * nz + z] = gd * cd * sE.bh[0] * idt;
+        co[11 * nz + z] = gd * (-(kdE / tau) * rhoE * ph.nu + 0.5 * dptE) * idt;
+        co[12 * nz + z] = gd / (2.0 * tau);
+    }
+
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.rhs[(long)v * L.nz + z] = rhs[v];
+    if (a.dbg_divF) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            a.dbg_divF[(long)v * L.nz + z] = divF[v];
+            a.dbg_src[(long)v * L.nz + z] = src[v];
+        }
+        if (a.dbg_sp) {
+            a.dbg_sp[3 * z + 0] = sq;
+            a.dbg_sp[3 * z + 1] = sdiv;
+            a.dbg_sp[3 * z + 2] = sdp;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ residual hook
+
+template <int NV, class G>
+__global__ __launch_bounds__(kBlock) void k_residual(StageArgs a, const double* P, double* R, double* rnorm)
+{
+    const long z = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (z >= a.L.nz) return;
+    const long cell = zone_cell(a.L, z);
+    ZoneC<NV, G> zc;
+    load_zone<NV, G>(a, z, cell, zc);
+    double p[NV], r[NV], pn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        p[v] = P[(long)v * a.L.nz + z];
+        pn[v] = a.Pn[(long)v * a.L.cells + cell];
+    }
+    zone_residual<NV, G>(p, zc, a.ph, r);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) R[(long)v * a.L.nz + z] = r[v];
+    if (rnorm) {
+        St<NV> sn;
+        derive<NV>(pn, zc.g, a.ph, sn);
+        const double urho = zc.g.gdet() * pn[RHO] * sn.ucon[0];
+        rnorm[z] = a.dtp * sqrt(sumsq<NV>(r)) / urho;
+    }
+}
+
+// ------------------------------------------------------------------ CFL
+
+template <int NV, class G>
+__global__ __launch_bounds__(kBlock) void k_cfl(Layout L, Phys ph, GeoTables geo, const double* P,
+                                                unsigned long long* out)
+{
+    __shared__ double red[kBlock];
+    const long z = (long)blockIdx.x * kBlock + threadIdx.x;
+    double t = 1e300;
+    if (z < L.nz) {
+        const long cell = zone_cell(L, z);
+        double p[NV];
+        load_cell<NV>(P, L.cells, cell, p);
+        G g;
+        if constexpr (!G::kFlat) load_geo(g, geo.centre, (size_t)(cell % ((long)L.N[0] * L.N[1])), geo.stride);
+        St<NV> s;
+        derive<NV>(p, g, ph, s);
+        double acc = cmax<NV, 1>(p, g, s, ph) / L.dx[0];
+        if (L.ndim >= 2) acc += cmax<NV, 2>(p, g, s, ph) / L.dx[1];
+        if (L.ndim >= 3) acc += cmax<NV, 3>(p, g, s, ph) / L.dx[2];
+        t = 1.0 / acc;
+    }
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMin(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// ------------------------------------------------------------------ utilities
+
+__global__ void k_zero_stats(DevStats* s)
+{
+    if (threadIdx.x == 0) {
+        s->iters[0] = s->iters[1] = 0;
+        s->n_fail = s->n_ls = s->n_unphys = s->zone_stages = s->resid_calls = 0;
+        s->max_resid_bits = 0;
+        s->max_iters = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stream_add(const double* __restrict__ a, const double* __restrict__ b,
+                                                       double* __restrict__ c, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (; i < n; i += stride) c[i] = a[i] + b[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_interior(Layout L, int nvar, const double* src, int sg, double* dst,
+                                                          int dg)
+{
+    const long z = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (z >= L.nz) return;
+    const long cell = zone_cell(L, z);
+    for (int v = 0; v < nvar; ++v) {
+        const double x = src[(long)v * (sg ? L.cells : L.nz) + (sg ? cell : z)];
+        dst[(long)v * (dg ? L.cells : L.nz) + (dg ? cell : z)] = x;
+    }
+}
+
+template <int NV, class G>
+hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
+{
+    const Layout& L = a.L;
+    const int nd = L.ndim;
+    // face ranges: along d the n_d + 1 faces of interior cells; across the
+    // other active directions one extra row each side (flux-CT needs them)
+    for (int d = 0; d < nd; ++d) {
+        int lo[3], cnt[3];
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) { lo[e] = L.g[e]; cnt[e] = L.n[e] + 1; }
+            else if (e < nd) { lo[e] = L.g[e] - 1; cnt[e] = L.n[e] + 2; }
+            else { lo[e] = 0; cnt[e] = 1; }
+        }
+        const long n = (long)cnt[0] * cnt[1] * cnt[2];
+        if (d == 0)
+            hipLaunchKernelGGL((k_flux<NV, G, 1>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
+                               cnt[0], cnt[1], cnt[2]);
+        else if (d == 1)
+            hipLaunchKernelGGL((k_flux<NV, G, 2>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
+                               cnt[0], cnt[1], cnt[2]);
+        else
+            hipLaunchKernelGGL((k_flux<NV, G, 3>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
+                               cnt[0], cnt[1], cnt[2]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t emf_t(const StageArgs& a, hipStream_t st)
+{
+    const Layout& L = a.L;
+    const int nd = L.ndim;
+    if (nd >= 2) {
+        const int c0 = L.n[0] + 1, c1 = L.n[1] + 1, c2 = nd == 3 ? L.n[2] + 1 : 1;
+        hipLaunchKernelGGL(k_emf, dim3(nblocks((long)c0 * c1 * c2)), dim3(kBlock), 0, st, a, c0, c1, c2);
+    }
+    return hipGetLastError();
+}
+
+template <int NV, class G>
+hipError_t rhs_t(const StageArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rhs<NV, G>), dim3(nblocks(a.L.nz)), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NV, class G>
+hipError_t explicit_stage_t(const StageArgs& a, hipStream_t st)
+{
+    hipError_t e = fluxes_t<NV, G>(a, st);
+    if (e == hipSuccess) e = emf_t(a, st);
+    if (e == hipSuccess) e = rhs_t<NV, G>(a, st);
+    return e;
+}
+
+}  // namespace
+
+hipError_t launch_fill_ghosts(const Layout& L, int nvar, const int bc[3], double* P, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_ghosts, dim3(nblocks(L.cells)), dim3(kBlock), 0, st, L, nvar, bc[0], bc[1], bc[2], P);
+    return hipGetLastError();
+}
+
+hipError_t launch_explicit_stage(const StageArgs& a, int nvar, int metric, hipStream_t st)
+{
+    if (nvar == 8) return metric == 0 ? explicit_stage_t<8, GeoMink>(a, st) : explicit_stage_t<8, GeoKS>(a, st);
+    return metric == 0 ? explicit_stage_t<10, GeoMink>(a, st) : explicit_stage_t<10, GeoKS>(a, st);
+}
+
+hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t st)
+{
+    if (nvar == 8) return metric == 0 ? fluxes_t<8, GeoMink>(a, st) : fluxes_t<8, GeoKS>(a, st);
+    return metric == 0 ? fluxes_t<10, GeoMink>(a, st) : fluxes_t<10, GeoKS>(a, st);
+}
+
+hipError_t launch_emf(const StageArgs& a, hipStream_t st) { return emf_t(a, st); }
+
+hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st)
+{
+    if (nvar == 8) return metric == 0 ? rhs_t<8, GeoMink>(a, st) : rhs_t<8, GeoKS>(a, st);
+    return metric == 0 ? rhs_t<10, GeoMink>(a, st) : rhs_t<10, GeoKS>(a, st);
+}
+
+hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const double* P, double* R, double* rnorm,
+                           hipStream_t st)
+{
+    const dim3 grid(nblocks(a.L.nz)), blk(kBlock);
+    if (nvar == 8) {
+        if (metric == 0) hipLaunchKernelGGL((k_residual<8, GeoMink>), grid, blk, 0, st, a, P, R, rnorm);
+        else hipLaunchKernelGGL((k_residual<8, GeoKS>), grid, blk, 0, st, a, P, R, rnorm);
+    } else {
+        if (metric == 0) hipLaunchKernelGGL((k_residual<10, GeoMink>), grid, blk, 0, st, a, P, R, rnorm);
+        else hipLaunchKernelGGL((k_residual<10, GeoKS>), grid, blk, 0, st, a, P, R, rnorm);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int nvar, int metric, const double* P,
+                      unsigned long long* out_bits, hipStream_t st)
+{
+    const dim3 grid(nblocks(L.nz)), blk(kBlock);
+    if (nvar == 8) {
+        if (metric == 0) hipLaunchKernelGGL((k_cfl<8, GeoMink>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        else hipLaunchKernelGGL((k_cfl<8, GeoKS>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+    } else {
+        if (metric == 0) hipLaunchKernelGGL((k_cfl<10, GeoMink>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        else hipLaunchKernelGGL((k_cfl<10, GeoKS>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_stats(DevStats* s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_add(const double* a, const double* b, double* c, size_t n, hipStream_t st)
+{
+    const long blocks = (long)std::min<size_t>((n + kBlock - 1) / kBlock, (size_t)256 * 64);
+    hipLaunchKernelGGL(k_stream_add, dim3((unsigned)std::max<long>(blocks, 1)), dim3(kBlock), 0, st, a, b, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_interior(const Layout& L, int nvar, const double* src, int src_ghosted, double* dst,
+                                int dst_ghosted, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_interior, dim3(nblocks(L.nz)), dim3(kBlock), 0, st, L, nvar, src, src_ghosted, dst,
+                       dst_ghosted);
+    return hipGetLastError();
+}
+
+}  // namespace grim

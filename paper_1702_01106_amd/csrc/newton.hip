@@ -1,0 +1,292 @@
+// The per-zone Newton-Raphson solve of grim (Sec. 3) for gfx950: one zone per
+// lane, everything in registers.
+//
+//   R(P) FP64 always (a8).  Jacobian by forward differences with the
+//   perturbation rule of Sec. 3.1 (a9): column j = (R(P_eps,j) - R(P))/h_j,
+//   h_j = P_eps,j - P_j.  Dense LU with partial pivoting (a10): row swaps are
+//   branch-free selects so J never leaves registers.  Quadratic backtracking
+//   line search (a11, Sec. 3.2).  Converged lanes go idle; the wave leaves
+//   the loop when every lane has (a12).  Statistics are reduced across the
+//   wave with shuffles and accumulated with one atomic per wave (a13).
+//
+// JT selects the precision of the difference quotients, the stored Jacobian
+// and the LU: double (the plain method) or float (mixed precision; the
+// residual, conserved variables, metric and Lorentz factor stay FP64).
+#include <hip/hip_runtime.h>
+
+#include "grim_internal.h"
+#include "grim_zone.h"
+
+namespace grim {
+
+namespace {
+
+constexpr int kWave = 64;
+
+// Solve A x = b in place (x returned in b) by Gaussian elimination with
+// partial pivoting.  Returns false on an exactly zero pivot.
+template <int N, typename T>
+__device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        T best = fabs(A[k][k]);
+        int p = k;
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const T v = fabs(A[i][k]);
+            const bool gt = v > best;
+            best = gt ? v : best;
+            p = gt ? i : p;
+        }
+        ok = ok && (best != T(0));
+        // swap rows k and p with selects (J stays in registers)
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const bool s = (p == i);
+#pragma unroll
+            for (int j = k; j < N; ++j) {
+                const T tk = A[k][j], ti = A[i][j];
+                A[k][j] = s ? ti : tk;
+                A[i][j] = s ? tk : ti;
+            }
+            const T tk = b[k], ti = b[i];
+            b[k] = s ? ti : tk;
+            b[i] = s ? tk : ti;
+        }
+        const T inv = T(1) / A[k][k];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const T f = A[i][k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < N; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
+            b[i] = fma(-f, b[k], b[i]);
+        }
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        T s = b[i];
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) s = fma(-A[i][j], b[j], s);
+        b[i] = s / A[i][i];
+    }
+    return ok;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ int wave_max(int x)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_maxu64(unsigned long long x)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+template <int NV, class G, typename JT>
+__global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
+{
+    const long z = (long)blockIdx.x * kWave + threadIdx.x;
+    const Layout& L = a.s.L;
+    const bool active = z < L.nz;
+    int iters = 0, ncalls = 0;
+    uint8_t fl = 0;
+    double rr = 0.0;
+
+    if (active) {
+        const long cell = zone_cell(L, z);
+        ZoneC<NV, G> zc;
+        load_zone<NV, G>(a.s, z, cell, zc);
+        const Phys& ph = a.s.ph;
+
+        double P[NV];
+        {
+            double pn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * L.cells + cell];
+            St<NV> sn;
+            derive<NV>(pn, zc.g, ph, sn);
+            // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
+            rr = a.s.dtp / (zc.g.gdet() * pn[RHO] * sn.ucon[0]);
+            if (a.guess) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) P[v] = a.guess[(long)v * L.nz + z];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) P[v] = pn[v];
+            }
+        }
+        const double nscale = rr;
+        // B rows: the explicit update is their exact root
+        {
+            const double f = a.s.dtp / zc.g.gdet();
+#pragma unroll
+            for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * f;
+        }
+
+        double R[NV];
+        zone_residual<NV, G>(P, zc, ph, R);
+        ++ncalls;
+        double r = nscale * sqrt(sumsq<NV>(R));
+        const double eps = a.eps;
+        for (;;) {
+            if (!isfinite(r)) { fl |= 16; break; }
+            if (r < a.tol) break;
+            if (iters >= a.k_max) { fl |= 1; break; }
+            // finite-difference Jacobian, column by column
+            JT J[NV][NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                double Pe[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) Pe[q] = P[q];
+                const double pj = P[j];
+                const bool small = fabs(pj) < 5.0 * eps;
+                double pe = small ? eps : (1.0 + eps) * pj;
+                double h = pe - pj;
+                if (h == 0.0) {
+                    pe = pj + eps;
+                    h = pe - pj;
+                }
+                Pe[j] = pe;
+                double Re[NV];
+                zone_residual<NV, G>(Pe, zc, ph, Re);
+                ++ncalls;
+                const double ih = 1.0 / h;
+#pragma unroll
+                for (int i = 0; i < NV; ++i) J[i][j] = (JT)((Re[i] - R[i]) * ih);
+            }
+            JT x[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) x[v] = (JT)(-R[v]);
+            if (!lu_solve<NV, JT>(J, x)) { fl |= 4; break; }
+            double dP[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dP[v] = (double)x[v];
+
+            // quadratic backtracking line search
+            const double f0 = r * r;
+            double lam = 1.0;
+            bool accepted = false, have = false;
+            double Pf[NV], Rf[NV], rf = 0.0;
+            for (int t = 0; t < a.ls_max; ++t) {
+                double Pt[NV], Rt[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], P[v]);
+                zone_residual<NV, G>(Pt, zc, ph, Rt);
+                ++ncalls;
+                const double rt = nscale * sqrt(sumsq<NV>(Rt));
+                if (isfinite(rt)) {
+                    have = true;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        Pf[v] = Pt[v];
+                        Rf[v] = Rt[v];
+                    }
+                    rf = rt;
+                    if (rt < r * (1.0 - a.eps_bt * lam)) {
+                        accepted = true;
+                        break;
+                    }
+                    lam = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
+                } else {
+                    lam *= 0.5;
+                }
+            }
+            if (!accepted) {
+                fl |= 2;
+                if (!have) {
+                    fl |= 16;
+                    ++iters;
+                    break;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                P[v] = Pf[v];
+                R[v] = Rf[v];
+            }
+            r = rf;
+            ++iters;
+        }
+        rr = r;
+        if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= 8;
+        if (a.s.floors) {
+            const int ii = (int)(z % L.n[0]);
+            const double r1 = exp(L.xs[0] + (ii + 0.5) * L.dx[0]);
+            const double rf = a.s.rho_fl * pow(r1, -1.5), uf = a.s.u_fl * pow(r1, -2.5);
+            if (!(P[RHO] >= rf)) P[RHO] = rf;
+            if (!(P[UU] >= uf)) P[UU] = uf;
+        }
+        if (a.out_ghosted) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + cell] = P[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = P[v];
+        }
+        if (a.iters) a.iters[z] = iters;
+        if (a.resid) a.resid[z] = rr;
+        if (a.flags) a.flags[z] = fl;
+    }
+
+    // wave-level statistics, one atomic per wave
+    if (a.stats) {
+        const double sit = wave_sum(active ? (double)iters : 0.0);
+        const int mit = wave_max(active ? iters : 0);
+        const double nf = wave_sum(active && (fl & (1 | 4 | 16)) ? 1.0 : 0.0);
+        const double nl = wave_sum(active && (fl & 2) ? 1.0 : 0.0);
+        const double nu = wave_sum(active && (fl & 8) ? 1.0 : 0.0);
+        const double na = wave_sum(active ? 1.0 : 0.0);
+        const double nc = wave_sum(active ? (double)ncalls : 0.0);
+        unsigned long long rb = 0;
+        if (active) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
+        rb = wave_maxu64(rb);
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.stats->iters[a.stage], (unsigned long long)sit);
+            atomicMax(&a.stats->max_iters, (unsigned)mit);
+            if (nf > 0) atomicAdd(&a.stats->n_fail, (unsigned long long)nf);
+            if (nl > 0) atomicAdd(&a.stats->n_ls, (unsigned long long)nl);
+            if (nu > 0) atomicAdd(&a.stats->n_unphys, (unsigned long long)nu);
+            atomicAdd(&a.stats->zone_stages, (unsigned long long)na);
+            atomicAdd(&a.stats->resid_calls, (unsigned long long)nc);
+            atomicMax(&a.stats->max_resid_bits, rb);
+        }
+    }
+}
+
+template <int NV, class G>
+hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
+{
+    const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
+    if (jac_f32)
+        hipLaunchKernelGGL((k_newton<NV, G, float>), grid, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st)
+{
+    if (nvar == 8) return metric == 0 ? newton_t<8, GeoMink>(a, jac_f32, st) : newton_t<8, GeoKS>(a, jac_f32, st);
+    return metric == 0 ? newton_t<10, GeoMink>(a, jac_f32, st) : newton_t<10, GeoKS>(a, jac_f32, st);
+}
+
+}  // namespace grim

@@ -1,0 +1,336 @@
+"""ctypes binding of libgrim (include/grim.h): same names, argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``libgrim.so``; this
+module only converts Python values, numpy arrays and PyTorch device tensors
+into the C call's plain pointers and sizes.  There is no fallback: if the
+library has not been built, :func:`load` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrim.so")
+
+GRIM_OK = 0
+GRIM_IDEAL_MHD, GRIM_EMHD = 8, 10
+GRIM_MINKOWSKI, GRIM_MKS_KERR = 0, 1
+GRIM_BC = {"periodic": 0, "outflow": 1, "polar": 2}
+GRIM_JAC = {"f64": 0, "f32": 1}
+FLAGS = {"NOT_CONVERGED": 1, "LS_EXHAUSTED": 2, "SINGULAR": 4, "UNPHYSICAL": 8, "NONFINITE": 16}
+
+
+class grim_config_t(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("ng", C.c_int),
+        ("model", C.c_int), ("metric", C.c_int),
+        ("x_start", C.c_double * 3), ("x_end", C.c_double * 3),
+        ("spin_a", C.c_double), ("mks_h", C.c_double),
+        ("bc", C.c_int * 3),
+        ("gamma", C.c_double), ("tau_R", C.c_double), ("chi", C.c_double), ("nu", C.c_double),
+        ("plm_theta", C.c_double),
+        ("tol", C.c_double), ("eps_fd", C.c_double), ("eps_bt", C.c_double),
+        ("k_max", C.c_int), ("ls_max", C.c_int),
+        ("jac_precision", C.c_int),
+        ("floors", C.c_int), ("rho_floor", C.c_double), ("u_floor", C.c_double),
+    ]
+
+
+class grim_stats_t(C.Structure):
+    _fields_ = [
+        ("mean_iters", C.c_double * 2), ("max_iters", C.c_int32), ("pad", C.c_int32),
+        ("n_fail", C.c_int64), ("n_ls_exhausted", C.c_int64), ("n_unphysical", C.c_int64),
+        ("max_resid", C.c_double), ("zone_stages", C.c_int64), ("n_resid_calls", C.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "mean_iters": [self.mean_iters[0], self.mean_iters[1]],
+            "max_iters": int(self.max_iters),
+            "n_fail": int(self.n_fail),
+            "n_ls_exhausted": int(self.n_ls_exhausted),
+            "n_unphysical": int(self.n_unphysical),
+            "max_resid": float(self.max_resid),
+            "zone_stages": int(self.zone_stages),
+            "n_resid_calls": int(self.n_resid_calls),
+        }
+
+
+_VP = C.c_void_p
+_D = C.c_double
+_lib = None
+
+
+class GrimError(RuntimeError):
+    pass
+
+
+def load():
+    """Load libgrim.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GrimError(f"{LIB_PATH} is not built: run `python -m paper_1702_01106_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    L.grim_create.argtypes = [C.POINTER(grim_config_t), _VP, C.POINTER(_VP)]
+    L.grim_destroy.argtypes = [_VP]
+    L.grim_last_error.argtypes = [_VP]
+    L.grim_last_error.restype = C.c_char_p
+    L.grim_last_global_error.restype = C.c_char_p
+    L.grim_device_bytes.argtypes = [_VP]
+    L.grim_device_bytes.restype = C.c_size_t
+    L.grim_set_prims.argtypes = [_VP, _VP, C.c_int]
+    L.grim_get_prims.argtypes = [_VP, _VP, C.c_int]
+    L.grim_cfl_dt.argtypes = [_VP, _D, C.POINTER(_D)]
+    L.grim_run.argtypes = [_VP, _D, C.c_int, C.c_int, C.POINTER(grim_stats_t)]
+    L.grim_residual.argtypes = [_VP, _VP, _VP, _D, _VP, _VP, _VP]
+    L.grim_stage_solve.argtypes = [_VP, _VP, _VP, _D, _VP, _VP, _VP, _VP, _VP]
+    L.grim_explicit.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.grim_get_zone_results.argtypes = [_VP, _VP, _VP, C.c_int]
+    L.grim_stream_add.argtypes = [_VP, _VP, _VP, _VP, C.c_size_t]
+    L.grim_profile.argtypes = [_VP, C.c_int]
+    L.grim_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["grim_create", "grim_destroy", "grim_last_error", "grim_last_global_error", "grim_device_bytes",
+            "grim_set_prims", "grim_get_prims", "grim_cfl_dt", "grim_run", "grim_residual", "grim_stage_solve",
+            "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_profile", "grim_kernel_times"]
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, host pointer of a numpy array, or NULL."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _check(ctx, rc, what):
+    if rc != GRIM_OK:
+        msg = load().grim_last_error(ctx) if ctx else load().grim_last_global_error()
+        raise GrimError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def config_from_workload(wl: dict) -> grim_config_t:
+    c = grim_config_t()
+    n = list(wl["n"]) + [1] * (3 - len(wl["n"]))
+    xs = list(wl["x_start"]) + [0.0] * (3 - len(wl["x_start"]))
+    xe = list(wl["x_end"]) + [1.0] * (3 - len(wl["x_end"]))
+    c.ndim = wl["ndim"]
+    c.n1, c.n2, c.n3 = n
+    c.ng = wl.get("ng", 2)
+    c.model = wl["nvar"]
+    c.metric = GRIM_MKS_KERR if wl.get("metric", "minkowski") == "mks" else GRIM_MINKOWSKI
+    for d in range(3):
+        c.x_start[d] = xs[d]
+        c.x_end[d] = xe[d]
+    c.spin_a = wl.get("spin", 0.0)
+    c.mks_h = wl.get("hslope", 0.3)
+    bc = (list(wl.get("bc", ["periodic"] * 3)) + ["periodic"] * 3)[:3]
+    for d in range(3):
+        c.bc[d] = GRIM_BC[bc[d]]
+    c.gamma = wl["gamma"]
+    c.tau_R = wl.get("tau_R", 1.0)
+    c.chi = wl.get("chi", 0.0)
+    c.nu = wl.get("nu", 0.0)
+    c.plm_theta = wl.get("plm_theta", 1.0)
+    c.tol = wl.get("tol", 1e-10)
+    c.eps_fd = wl.get("eps_fd", 1.4901161193847656e-08)
+    c.eps_bt = wl.get("eps_bt", 1e-4)
+    c.k_max = wl.get("k_max", 20)
+    c.ls_max = wl.get("ls_max", 10)
+    c.jac_precision = GRIM_JAC[wl.get("jac", "f64")]
+    c.floors = 1 if wl.get("floors", False) else 0
+    c.rho_floor = wl.get("rho_floor", 1e-5)
+    c.u_floor = wl.get("u_floor", 1e-7)
+    return c
+
+
+# ---------------------------------------------------------------- C names
+
+def grim_create(cfg: grim_config_t, stream_handle=None):
+    ctx = _VP()
+    rc = load().grim_create(C.byref(cfg), stream_handle, C.byref(ctx))
+    _check(None, rc, "grim_create")
+    return ctx
+
+
+def grim_destroy(ctx):
+    load().grim_destroy(ctx)
+
+
+def grim_set_prims(ctx, P, on_device):
+    _check(ctx, load().grim_set_prims(ctx, _ptr(P), int(on_device)), "grim_set_prims")
+
+
+def grim_get_prims(ctx, P, on_device):
+    _check(ctx, load().grim_get_prims(ctx, _ptr(P), int(on_device)), "grim_get_prims")
+
+
+def grim_cfl_dt(ctx, cfl):
+    dt = _D()
+    _check(ctx, load().grim_cfl_dt(ctx, cfl, C.byref(dt)), "grim_cfl_dt")
+    return dt.value
+
+
+def grim_run(ctx, dt, nsteps, use_graph=True, want_stats=True):
+    st = grim_stats_t()
+    rc = load().grim_run(ctx, dt, int(nsteps), int(use_graph), C.byref(st) if want_stats else None)
+    _check(ctx, rc, "grim_run")
+    return st.as_dict() if want_stats else None
+
+
+def grim_residual(ctx, Pn, PE, dtp, P, R, rnorm=None):
+    _check(ctx, load().grim_residual(ctx, _ptr(Pn), _ptr(PE), dtp, _ptr(P), _ptr(R), _ptr(rnorm)), "grim_residual")
+
+
+def grim_stage_solve(ctx, Pn, PE, dtp, guess, P_out, iters=None, resid=None, flags=None):
+    rc = load().grim_stage_solve(ctx, _ptr(Pn), _ptr(PE), dtp, _ptr(guess), _ptr(P_out), _ptr(iters),
+                                 _ptr(resid), _ptr(flags))
+    _check(ctx, rc, "grim_stage_solve")
+
+
+def grim_explicit(ctx, PE, divF, srcE, emhd_sp=None):
+    _check(ctx, load().grim_explicit(ctx, _ptr(PE), _ptr(divF), _ptr(srcE), _ptr(emhd_sp)), "grim_explicit")
+
+
+def grim_get_zone_results(ctx, flags, iters, on_device):
+    _check(ctx, load().grim_get_zone_results(ctx, _ptr(flags), _ptr(iters), int(on_device)), "grim_get_zone_results")
+
+
+def grim_stream_add(ctx, a, b, c, n):
+    _check(ctx, load().grim_stream_add(ctx, _ptr(a), _ptr(b), _ptr(c), int(n)), "grim_stream_add")
+
+
+KERNEL_GROUPS = ["ghost_fill", "face_flux", "flux_ct_emf", "stage_rhs", "newton"]
+
+
+def grim_profile(ctx, enable):
+    _check(ctx, load().grim_profile(ctx, int(enable)), "grim_profile")
+
+
+def grim_kernel_times(ctx):
+    ms = (C.c_double * 5)()
+    n = (C.c_int64 * 5)()
+    _check(ctx, load().grim_kernel_times(ctx, ms, n, 5), "grim_kernel_times")
+    return {KERNEL_GROUPS[i]: (float(ms[i]), int(n[i])) for i in range(5)}
+
+
+def grim_device_bytes(ctx):
+    return int(load().grim_device_bytes(ctx))
+
+
+# ---------------------------------------------------------------- convenience
+
+class Context:
+    """One libgrim context for a workload dict; tensors are torch (cuda) float64."""
+
+    def __init__(self, wl: dict, stream=None):
+        import torch
+
+        self.torch = torch
+        self.wl = dict(wl)
+        self.cfg = config_from_workload(self.wl)
+        n = list(wl["n"]) + [1] * (3 - len(wl["n"]))
+        self.nvar = wl["nvar"]
+        self.shape = (self.nvar, n[2], n[1], n[0])
+        self.nz = n[0] * n[1] * n[2]
+        self.stream = stream
+        handle = None if stream is None else _VP(stream.cuda_stream)
+        self.ctx = grim_create(self.cfg, handle)
+
+    def close(self):
+        if self.ctx:
+            grim_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, x, dtype=None):
+        t = self.torch
+        if isinstance(x, np.ndarray):
+            x = t.from_numpy(np.ascontiguousarray(x))
+        x = x.to(device="cuda", dtype=dtype or t.float64).contiguous()
+        return x
+
+    def empty(self, shape=None, dtype=None):
+        return self.torch.empty(shape or self.shape, dtype=dtype or self.torch.float64, device="cuda")
+
+    def set_prims(self, P):
+        if isinstance(P, np.ndarray):
+            a = np.ascontiguousarray(P, dtype=np.float64)
+            assert a.size == self.nvar * self.nz
+            grim_set_prims(self.ctx, a, False)
+        else:
+            d = self._dev(P)
+            assert d.numel() == self.nvar * self.nz
+            grim_set_prims(self.ctx, d, True)
+
+    def get_prims(self):
+        out = np.empty(self.shape)
+        grim_get_prims(self.ctx, out, False)
+        return out
+
+    def get_prims_device(self, out=None):
+        out = self.empty() if out is None else out
+        grim_get_prims(self.ctx, out, True)
+        return out
+
+    def cfl_dt(self, cfl):
+        return grim_cfl_dt(self.ctx, cfl)
+
+    def run(self, dt, nsteps, use_graph=True, want_stats=True):
+        return grim_run(self.ctx, dt, nsteps, use_graph, want_stats)
+
+    def residual(self, Pn, PE, dtp, P):
+        Pn, PE, P = self._dev(Pn), self._dev(PE), self._dev(P)
+        R = self.empty()
+        rn = self.empty((self.nz,))
+        grim_residual(self.ctx, Pn, PE, dtp, P, R, rn)
+        return R, rn
+
+    def stage_solve(self, Pn, PE, dtp, guess=None):
+        t = self.torch
+        Pn, PE = self._dev(Pn), self._dev(PE)
+        g = None if guess is None else self._dev(guess)
+        out = self.empty()
+        it = t.empty((self.nz,), dtype=t.int32, device="cuda")
+        rr = self.empty((self.nz,))
+        fl = t.empty((self.nz,), dtype=t.uint8, device="cuda")
+        grim_stage_solve(self.ctx, Pn, PE, dtp, g, out, it, rr, fl)
+        return out, it, rr, fl
+
+    def explicit(self, PE):
+        PE = self._dev(PE)
+        divF = self.empty()
+        src = self.empty()
+        sp = self.empty((self.nz, 3))
+        grim_explicit(self.ctx, PE, divF, src, sp)
+        return divF, src, sp
+
+    def zone_results(self):
+        fl = np.empty(self.nz, dtype=np.uint8)
+        it = np.empty(self.nz, dtype=np.int32)
+        grim_get_zone_results(self.ctx, fl, it, False)
+        return fl, it
+
+    def profile(self, enable):
+        grim_profile(self.ctx, enable)
+
+    def kernel_times(self):
+        return grim_kernel_times(self.ctx)
+
+    def device_bytes(self):
+        return grim_device_bytes(self.ctx)

@@ -16,5 +16,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
-    oracle.build()
+    oracle.Oracle.lib()  # builds only if the library is missing or stale
     return oracle

@@ -1,0 +1,84 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/grim.h declares, and rejects invalid configurations before touching
+a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1702_01106_amd import grim
+from paper_1702_01106_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(grim_\w+)\s*\(", src, re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(grim.LIB_PATH):
+        pytest.skip("libgrim.so not built")
+    return grim.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = _declared()
+    assert len(decl) >= 14
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert decl == set(grim.exported_symbols())
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    """ctypes mirrors of grim_config_t / grim_stats_t have the header's field
+    offsets (checked with a C program compiled against include/grim.h)."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "grim.h"', "int main(void){"]
+    for cname, py in (("grim_config_t", grim.grim_config_t), ("grim_stats_t", grim.grim_stats_t)):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.split("\n") if l)
+    for cname, py in (("grim_config_t", grim.grim_config_t), ("grim_stats_t", grim.grim_stats_t)):
+        assert int(out[cname]) == C.sizeof(py)
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (dict(ndim=4), "ndim"),
+    (dict(ng=1), "ng"),
+    (dict(nvar=9), "model"),
+    (dict(gamma=1.0), "gamma"),
+    (dict(chi=0.0), "EMHD"),
+    (dict(ls_max=0), "ls_max"),
+    (dict(n=[256, 0]), "no zones"),
+])
+def test_invalid_config_rejected_before_device(lib, mutate, msg):
+    wl = W.workload("emhd2d_modes_256")
+    wl.update(mutate)
+    cfg = grim.config_from_workload(wl)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_create(cfg, None)
+    assert msg in str(e.value)
+
+
+def test_oracle_not_imported_by_product():
+    """The product path never imports the oracle."""
+    for f in ("grim.py", "workloads.py", "build.py", "__init__.py"):
+        src = open(os.path.join(ROOT, "paper_1702_01106_amd", f)).read()
+        assert "oracle" not in src.replace("oracle's", "")
