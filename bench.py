@@ -49,16 +49,21 @@ def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) ->
             + ls_trials * 2 * n)
 
 
-def _source_hash(path: str) -> str:
+NEWTON_SOURCES = ["newton.hip", "grim_zone.h", "grim_device.h", "grim_internal.h"]
+
+
+def newton_source_hash() -> str:
+    """Hash of the sources the Newton kernel is compiled from."""
     h = hashlib.sha256()
-    with open(path, "rb") as f:
-        h.update(f.read())
+    for f in NEWTON_SOURCES:
+        with open(os.path.join(ROOT, "paper_1702_01106_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_src: str):
+def traffic_from_profiles():
     """HBM bytes per Newton launch from committed rocprofv3 counters, if they
-    were taken on the current kernel source; otherwise None."""
+    were taken on the current kernel sources; otherwise None."""
     p = os.path.join(ROOT, "profiles", "newton_emhd2d_256_traffic.json")
     if not os.path.exists(p):
         return None
@@ -66,7 +71,7 @@ def traffic_from_profiles(kernel_src: str):
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if d.get("source_sha256_16") != _source_hash(kernel_src):
+    if d.get("newton_source_sha256_16") != newton_source_hash():
         return None
     return d.get("bytes_per_launch")
 
@@ -92,6 +97,28 @@ def cpu_baseline(wl: dict, P0, dt: float, steps: int) -> dict:
         "seconds": t,
         "mean_iters": st["mean_iters"],
     }
+
+
+def stream_probe(grim, wl, n: int = 1 << 26, reps: int = 20) -> dict:
+    """STREAM c = a + b over n doubles per array (Sec. 7.2's yardstick),
+    through the library's own kernel; bytes = 3 * 8 * n per launch."""
+    import torch
+
+    ctx = grim.Context(wl)
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    grim.grim_stream_add(ctx.ctx, a, b, c, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grim.grim_stream_add(ctx.ctx, a, b, c, n)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ok = bool(torch.equal(c, a + b))
+    ctx.close()
+    return {"gbs": 3 * 8 * n * reps / t / 1e9, "bytes_per_launch": 3 * 8 * n, "exact": ok}
 
 
 def timed_run(grim, W, wl, P0, steps, warmup):
@@ -125,7 +152,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="emhd2d_modes_256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -155,14 +182,13 @@ def main() -> int:
     per_launch_flops = flops / max(n_newton, 1)
     avg_s = ms_newton / max(n_newton, 1) * 1e-3
     achieved = per_launch_flops / avg_s / 1e12
-    kernel_src = os.path.join(ROOT, "paper_1702_01106_amd", "csrc", "newton.hip")
     roofline = {
         "bound": "alu",
         "achieved": achieved,
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
-        "traffic": traffic_from_profiles(kernel_src),
+        "traffic": traffic_from_profiles(),
         "kernel": f"k_newton<{nvar}, Minkowski, f64>",
         "avg_launch_us": avg_s * 1e6,
         "flops_per_launch": per_launch_flops,
@@ -188,6 +214,7 @@ def main() -> int:
         "kernel_ms": {k: v[0] for k, v in times.items()},
         "roofline": roofline,
     }
+    out["stream"] = stream_probe(grim, wl)
     if not args.no_variants:
         wl32 = dict(wl, jac="f32")
         _, t32, st32, _, times32 = timed_run(grim, W, wl32, P0, args.steps, args.warmup)

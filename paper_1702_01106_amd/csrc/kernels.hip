@@ -157,7 +157,7 @@ __device__ __forceinline__ void load_cell(const double* P, long cells, long m, d
 //   rhs_v = U_v(P_n)/dt' - divF_v(P^E) + S^E_v(P^E)
 // plus, for EMHD, every P-independent part of the relaxation sources folded
 // into rhs_q, rhs_DP, and the coefficients the Newton residual needs.
-template <int NV, class G>
+template <int NV, class G, int ND>
 __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
 {
     const long z = (long)blockIdx.x * kBlock + threadIdx.x;
@@ -169,13 +169,14 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
     const int i = ii + L.g[0], j = jj + L.g[1], k = kk + L.g[2];
     const long m = L.cell(i, j, k);
     const long C = L.cells;
-    const int nd = L.ndim;
+    constexpr int nd = ND;
 
     // divergence of the face fluxes, B rows from the flux-CT EMFs
     double divF[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         double s = 0.0;
+#pragma unroll
         for (int d = 0; d < nd; ++d) {
             const long st = L.stride(d);
             double fr, fl;
@@ -253,9 +254,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
         double X0[8];
         emhd_point<NV>(PE, g, a.ph, X0);
         double dX[3][8];
+#pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int q = 0; q < 8; ++q) dX[d][q] = 0.0;
+#pragma unroll
         for (int d = 0; d < nd; ++d) {
             const long st = L.stride(d);
             double Pm[NV], Pp[NV], Xm[8], Xp[8];
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
         }
         const double theta = X0[0];
         double a1 = 0.0, a2 = 0.0, b1 = 0.0, divs = 0.0;
+#pragma unroll
         for (int d = 0; d < nd; ++d) {
             a1 += sE.bh[d + 1] * dX[d][0];
 #pragma unroll
@@ -485,7 +489,10 @@ hipError_t emf_t(const StageArgs& a, hipStream_t st)
 template <int NV, class G>
 hipError_t rhs_t(const StageArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_rhs<NV, G>), dim3(nblocks(a.L.nz)), dim3(kBlock), 0, st, a);
+    const dim3 grid(nblocks(a.L.nz)), blk(kBlock);
+    if (a.L.ndim == 1) hipLaunchKernelGGL((k_rhs<NV, G, 1>), grid, blk, 0, st, a);
+    else if (a.L.ndim == 2) hipLaunchKernelGGL((k_rhs<NV, G, 2>), grid, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_rhs<NV, G, 3>), grid, blk, 0, st, a);
     return hipGetLastError();
 }
 
