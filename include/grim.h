@@ -61,6 +61,14 @@ extern "C" {
 /* precision of the Jacobian difference quotients, storage and LU */
 #define GRIM_JAC_F64 0
 #define GRIM_JAC_F32 1
+/* initial guess of the Newton solve */
+#define GRIM_GUESS_PN 0
+#define GRIM_GUESS_MLP 1
+/* learned-guess network: inputs, hidden width, outputs, parameter count */
+#define GRIM_MLP_IN 32
+#define GRIM_MLP_HIDDEN 128
+#define GRIM_MLP_OUT 16
+#define GRIM_MLP_PARAMS 22880
 /* per-zone flags */
 #define GRIM_FLAG_NOT_CONVERGED 1
 #define GRIM_FLAG_LS_EXHAUSTED 2
@@ -92,6 +100,7 @@ typedef struct {
     int k_max;           /* maximum Newton iterations                        */
     int ls_max;          /* maximum line-search trials per iteration         */
     int jac_precision;   /* GRIM_JAC_F64 or GRIM_JAC_F32                     */
+    int guess;           /* GRIM_GUESS_PN or GRIM_GUESS_MLP                  */
     int floors;          /* 1: rho >= rho_floor r^-3/2, u >= u_floor r^-5/2   */
     double rho_floor, u_floor;
 } grim_config_t;
@@ -107,7 +116,18 @@ typedef struct {
     double max_resid;       /* largest final scaled residual norm            */
     int64_t zone_stages;    /* zones x stages accumulated                    */
     int64_t n_resid_calls;  /* residual evaluations R(P), summed over zones  */
+    int64_t n_fallback;     /* zones whose learned guess was rejected        */
 } grim_stats_t;
+
+/* Adam training of the learned-guess network. */
+typedef struct {
+    int epochs;
+    int batch;           /* rows per step                                     */
+    int n_used;          /* outputs that enter the loss (5 ideal, 7 EMHD)     */
+    int pad;
+    double lr, beta1, beta2, eps;
+    uint64_t seed;       /* shuffling                                         */
+} grim_train_cfg_t;
 
 /* Create a context: validates cfg, allocates device buffers (ghosted
  * primitive arrays, face fluxes, edge EMFs, stage right-hand sides, per-zone
@@ -174,6 +194,50 @@ int grim_get_zone_results(grim_ctx_t* ctx, uint8_t* flags, int32_t* iters, int o
  * EMFs, 3 stage right-hand side, 4 Newton solve (n = 5 entries). */
 int grim_profile(grim_ctx_t* ctx, int enable);
 int grim_kernel_times(grim_ctx_t* ctx, double* ms, int64_t* launches, int n);
+
+/* ---- learned initial guess (spec: learned part) -------------------
+ * Network 32 -> 128 -> 128 -> 16 with GELU, parameters one FP32 vector of
+ * GRIM_MLP_PARAMS values: W1 [32][128], b1, W2 [128][128], b2, W3 [128][16],
+ * b3, x_mean [32], x_istd [32], y_scale [16];
+ *   y = (gelu(gelu(((x - x_mean) x_istd) W1 + b1) W2 + b2) W3 + b3) y_scale.
+ * Inputs per zone (dimensionless): (dt' rhs_v - U_v(P_n)) / U_rho(P_n) for
+ * every row v, u/rho, utilde^i, B^i/sqrt(rho), q/u, DP/u (EMHD), and the lapse,
+ * g^{01}, g^{11} in the last three slots.  Outputs: (rho - rho_n)/rho_n,
+ * (u - u_n)/u_n, utilde - utilde_n, (q - q_n)/u_n, (DP - DP_n)/u_n.
+ * With cfg.guess = GRIM_GUESS_MLP each stage evaluates the network (BF16
+ * matrix cores, FP32 accumulation) and each zone starts Newton from the
+ * prediction if its residual norm is below that of P_n, and falls back to P_n
+ * otherwise or if the solve from the prediction fails (stats.n_fallback).
+ * Errors: GRIM_E_STATE if the guess is requested before weights are set. */
+
+/* Copy n = GRIM_MLP_PARAMS FP32 values in from / out to host memory. */
+int grim_mlp_set_weights(grim_ctx_t* ctx, const float* w, size_t n);
+int grim_mlp_get_weights(grim_ctx_t* ctx, float* w, size_t n);
+
+/* Inference on n rows: X [n][32] -> Y [n][16], device pointers, BF16 matrix
+ * cores with FP32 accumulation (the path the solver uses).  Synchronises. */
+int grim_mlp_forward(grim_ctx_t* ctx, const float* X, int64_t n, float* Y);
+
+/* FP32 gradient of sum(dY * y(X)) with respect to all parameters (zero for the
+ * normalisation entries).  X [n][32], dY [n][16], dW [GRIM_MLP_PARAMS], device
+ * pointers.  Synchronises. */
+int grim_mlp_backward(grim_ctx_t* ctx, const float* X, const float* dY, int64_t n, float* dW);
+
+/* Adam on the mean squared error over the first n_used outputs, on n pairs
+ * X [n][32], T [n][16] (device); shuffled each epoch; FP32 master weights,
+ * normalisation entries fixed.  loss_hist (host, cfg->epochs doubles, may be
+ * NULL) receives the mean training loss of every epoch.  Synchronises. */
+int grim_mlp_train(grim_ctx_t* ctx, const float* X, const float* T, int64_t n, const grim_train_cfg_t* cfg,
+                   double* loss_hist);
+
+/* Training pairs from the plain FP64 solver: run nsteps full steps of size dt
+ * (eager, guess P_n) and after every stage store the network inputs and the
+ * scaled target (P - P_n) of the zones z = phase (mod stride), phase advancing
+ * by one per stage, into X [cap][32], T [cap][16] (device).  *count receives
+ * the number of pairs produced (those beyond cap are dropped).  Advances the
+ * state. */
+int grim_collect_pairs(grim_ctx_t* ctx, double dt, int nsteps, int stride, float* X, float* T, int64_t cap,
+                       int64_t* count);
 
 /* STREAM c = a + b over n doubles (the sustained-bandwidth yardstick of
  * Sec. 7.2).  a, b, c device pointers.  Enqueued, not timed. */

@@ -732,7 +732,8 @@ void oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x, const d
  *  - stop when ||R|| < tol (iters = number of linear solves), or at k_max
  *  - Jacobian by oracle_fd_jacobian
  *  - line search: accept if ||R(P + lam dP)|| < ||R(P)|| (1 - eps_bt lam);
- *    otherwise lam <- quadratic backtrack; a non-finite trial halves lam;
+ *    otherwise lam <- quadratic backtrack clamped to [0.1 lam, 0.5 lam];
+ *    a non-finite trial halves lam;
  *    after ls_max trials the last finite trial is taken (flag LS_EXHAUSTED). */
 int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nscale, double tol, double eps,
                           double eps_bt, int k_max, int ls_max, int32_t* iters, double* resid, uint8_t* flags)
@@ -762,7 +763,14 @@ int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nsca
                 for (int q = 0; q < n; ++q) { xf[q] = xt[q]; Rf[q] = Rt[q]; }
                 rf = rt;
                 if (rt < r * (1.0 - eps_bt * lam)) { accepted = 1; break; }
-                lam = oracle_ls_lambda(f0, rt * rt, lam);
+                /* minimiser of the quadratic model, safeguarded to
+                 * [0.1, 0.5] of the previous lambda (reading: the paper's
+                 * update has no lower bound; without one, a full step far
+                 * worse than f(0) yields lambda ~ 1e-4 and Newton stalls) */
+                double ln = oracle_ls_lambda(f0, rt * rt, lam);
+                if (!(ln >= 0.1 * lam)) ln = 0.1 * lam;
+                if (ln > 0.5 * lam) ln = 0.5 * lam;
+                lam = ln;
             } else {
                 lam *= 0.5;
             }

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrim.so")
-SOURCES = ["abi.hip", "kernels.hip", "geometry.hip", "newton.hip"]
+SOURCES = ["abi.hip", "kernels.hip", "geometry.hip", "newton.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -42,6 +44,19 @@ struct grim_ctx {
     double* geo_centre = nullptr;
     double* geo_face[3] = {nullptr, nullptr, nullptr};
     double* geo_conn = nullptr;
+    // learned guess
+    float* mlp_p = nullptr;              // FP32 parameters
+    unsigned short* mlp_w[3] = {nullptr, nullptr, nullptr};  // transposed BF16 weights
+    float* mlp_x = nullptr;              // per-zone inputs [nz][32]
+    float* mlp_y = nullptr;              // per-zone outputs [nz][16]
+    bool mlp_set = false;
+    grim::MlpWork work{};
+    float* mlp_grad = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    int* mlp_idx = nullptr;
+    long mlp_idx_cap = 0;
+    double* dloss = nullptr;
     size_t bytes = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     double graph_dt = 0.0;
@@ -103,7 +118,10 @@ void release(grim_ctx* c)
     if (c->own_st && c->st) hipStreamDestroy(c->st);
     void* ptrs[] = {c->P[0], c->P[1], c->F[0], c->F[1], c->F[2], c->E[0], c->E[1], c->E[2], c->rhs, c->coef,
                     c->interior, c->hookP[0], c->hookP[1], c->iters, c->resid, c->flags, c->stats, c->u64,
-                    c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn};
+                    c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn, c->mlp_p,
+                    c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->mlp_x, c->mlp_y, c->mlp_grad, c->adam_m, c->adam_v,
+                    c->mlp_idx, c->dloss, c->work.xh, c->work.tb, c->work.z1, c->work.h1, c->work.z2, c->work.h2,
+                    c->work.o, c->work.d_o, c->work.dh, c->work.dh1};
     for (void* p : ptrs)
         if (p) hipFree(p);
 }
@@ -132,6 +150,7 @@ int validate(const grim_config_t* g, std::string& why)
     if (!(g->tol > 0) || !(g->eps_fd > 0) || !(g->eps_bt >= 0)) return why = "bad tolerances", 1;
     if (g->k_max < 0 || g->ls_max < 1) return why = "k_max >= 0 and ls_max >= 1 required", 1;
     if (g->jac_precision != GRIM_JAC_F64 && g->jac_precision != GRIM_JAC_F32) return why = "bad jac_precision", 1;
+    if (g->guess != GRIM_GUESS_PN && g->guess != GRIM_GUESS_MLP) return why = "bad guess", 1;
     const double zones = (double)n[0] * n[1] * n[2];
     if (zones > 2.0e9) return why = "too many zones", 1;
     return 0;
@@ -197,10 +216,24 @@ struct Timed {
     }
 };
 
-// One stage: flux stage on PE (ghosts of PE must be filled), then Newton.
-int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, int stage, hipStream_t st)
+// Where a stage stores training pairs (grim_collect_pairs).
+struct Collect {
+    int stride;
+    int phase;
+    float* X;
+    float* T;
+    long cap;
+    long count;
+};
+
+// One stage: flux stage on PE (ghosts of PE must be filled), then Newton
+// (from the learned guess when cfg.guess asks for it).
+int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, int stage, hipStream_t st,
+                  Collect* col = nullptr)
 {
     StageArgs s = stage_args(c, Pn, PE, dtp);
+    const bool net = c->cfg.guess == GRIM_GUESS_MLP && !col;
+    if (net || col) s.mlp_x = c->mlp_x;
     if (c->timing) {
         {
             Timed t(c, 1, st);
@@ -217,17 +250,31 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     } else {
         HIP_TRY(c, grim::launch_explicit_stage(s, c->nvar, c->cfg.metric, st));
     }
+    if (net) {
+        Timed t(c, 5, st);
+        HIP_TRY(c, grim::mlp_infer(c->mlp_x, c->L.nz, c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->mlp_y, st));
+    }
     NewtonArgs n = newton_args(c, s);
     n.out = out;
     n.out_ghosted = 1;
     n.stage = stage;
-    Timed t(c, 4, st);
-    HIP_TRY(c, grim::launch_newton(n, c->nvar, c->cfg.metric, c->cfg.jac_precision, st));
+    n.mlp_y = net ? c->mlp_y : nullptr;
+    {
+        Timed t(c, 4, st);
+        HIP_TRY(c, grim::launch_newton(n, c->nvar, c->cfg.metric, c->cfg.jac_precision, st));
+    }
+    if (col) {
+        HIP_TRY(c, grim::launch_collect(s, c->nvar, out, 1, col->stride, col->phase, col->X, col->T, col->count,
+                                        col->cap, st));
+        const long nz = c->L.nz;
+        col->count += col->phase < nz ? (nz - 1 - col->phase) / col->stride + 1 : 0;
+        col->phase = (col->phase + 1) % col->stride;
+    }
     return GRIM_OK;
 }
 
 // One full step from buffer `from` into the other buffer, enqueued on st.
-int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st)
+int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st, Collect* col = nullptr)
 {
     double* A = c->P[from];
     double* B = c->P[1 - from];
@@ -236,7 +283,7 @@ int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st)
         Timed t(c, 0, st);
         HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, A, st));
     }
-    int rc = enqueue_stage(c, A, A, 0.5 * dt, B, 0, st);
+    int rc = enqueue_stage(c, A, A, 0.5 * dt, B, 0, st, col);
     if (rc) return rc;
     {
         Timed t(c, 0, st);
@@ -244,7 +291,40 @@ int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st)
     }
     // stage 2 writes P_{n+1} over P^E = P_{n+1/2}: each lane reads its own
     // zone of P^E before writing it, and nothing else reads P^E then.
-    return enqueue_stage(c, A, B, dt, B, 1, st);
+    return enqueue_stage(c, A, B, dt, B, 1, st, col);
+}
+
+int ensure_mlp_zone_buffers(grim_ctx* c)
+{
+    int rc = GRIM_OK;
+    if (!c->mlp_x) rc = dalloc(c, &c->mlp_x, (size_t)c->L.nz * grim::kMlpIn);
+    if (!rc && !c->mlp_y) rc = dalloc(c, &c->mlp_y, (size_t)c->L.nz * grim::kMlpOut);
+    return rc;
+}
+
+int ensure_mlp_train_buffers(grim_ctx* c, int cap)
+{
+    grim::MlpWork& w = c->work;
+    if (w.cap < cap) {
+        float** bufs[] = {&w.xh, &w.tb, &w.z1, &w.h1, &w.z2, &w.h2, &w.o, &w.d_o, &w.dh, &w.dh1};
+        const int widths[] = {grim::kMlpIn, grim::kMlpOut, grim::kMlpHidden, grim::kMlpHidden, grim::kMlpHidden,
+                              grim::kMlpHidden, grim::kMlpOut, grim::kMlpOut, grim::kMlpHidden, grim::kMlpHidden};
+        for (int i = 0; i < 10; ++i) {
+            if (*bufs[i]) {
+                hipFree(*bufs[i]);
+                *bufs[i] = nullptr;
+            }
+            int rc = dalloc(c, bufs[i], (size_t)cap * widths[i]);
+            if (rc) return rc;
+        }
+        w.cap = cap;
+    }
+    int rc = GRIM_OK;
+    if (!c->mlp_grad) rc = dalloc(c, &c->mlp_grad, (size_t)grim::kMlpParams);
+    if (!rc && !c->adam_m) rc = dalloc(c, &c->adam_m, (size_t)grim::kMlpTrainable);
+    if (!rc && !c->adam_v) rc = dalloc(c, &c->adam_v, (size_t)grim::kMlpTrainable);
+    if (!rc && !c->dloss) rc = dalloc(c, &c->dloss, 1);
+    return rc;
 }
 
 int ensure_hook_buffers(grim_ctx* c)
@@ -358,6 +438,11 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     if (!rc) rc = dalloc(c, &c->flags, (size_t)L.nz);
     if (!rc) rc = dalloc(c, &c->stats, 1);
     if (!rc) rc = dalloc(c, &c->u64, 4);
+    if (!rc) rc = dalloc(c, &c->mlp_p, (size_t)grim::kMlpParams);
+    if (!rc) rc = dalloc(c, &c->mlp_w[0], (size_t)grim::kMlpHidden * grim::kMlpIn);
+    if (!rc) rc = dalloc(c, &c->mlp_w[1], (size_t)grim::kMlpHidden * grim::kMlpHidden);
+    if (!rc) rc = dalloc(c, &c->mlp_w[2], (size_t)32 * grim::kMlpHidden);
+    if (!rc && cfg->guess == GRIM_GUESS_MLP) rc = ensure_mlp_zone_buffers(c);
     if (!rc && cfg->metric == GRIM_MKS_KERR) {
         const size_t s = (size_t)L.N[0] * L.N[1];
         rc = dalloc(c, &c->geo_centre, grim::kGeoDoubles * s);
@@ -451,6 +536,8 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
 {
     if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
     if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return fail(c, GRIM_E_INVALID_ARG, "bad dt or nsteps");
+    if (c->cfg.guess == GRIM_GUESS_MLP && !c->mlp_set)
+        return fail(c, GRIM_E_STATE, "learned guess requested but no network weights were set");
     HIP_TRY(c, grim::launch_zero_stats(c->stats, c->st));
     if (use_graph && nsteps > 0 && !c->timing) {
         if (c->graph_dt != dt || !c->graph[0]) {
@@ -503,6 +590,7 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
         stats->max_resid = mr;
         stats->zone_stages = (int64_t)d.zone_stages;
         stats->n_resid_calls = (int64_t)d.resid_calls;
+        stats->n_fallback = (int64_t)d.n_fallback;
     }
     return GRIM_OK;
 }
@@ -573,7 +661,7 @@ int grim_profile(grim_ctx_t* c, int enable)
 int grim_kernel_times(grim_ctx_t* c, double* ms, int64_t* launches, int n)
 {
     if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
-    if (!ms || !launches || n < 5) return fail(c, GRIM_E_INVALID_ARG, "need 5-entry output arrays");
+    if (!ms || !launches || n < 6) return fail(c, GRIM_E_INVALID_ARG, "need 6-entry output arrays");
     for (int i = 0; i < n; ++i) {
         ms[i] = 0.0;
         launches[i] = 0;
@@ -589,6 +677,121 @@ int grim_kernel_times(grim_ctx_t* c, double* ms, int64_t* launches, int n)
         hipEventDestroy(m.b);
     }
     c->marks.clear();
+    return GRIM_OK;
+}
+
+int grim_mlp_set_weights(grim_ctx_t* c, const float* w, size_t n)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!w || n != (size_t)grim::kMlpParams) return fail(c, GRIM_E_INVALID_ARG, "need GRIM_MLP_PARAMS values");
+    HIP_TRY(c, hipMemcpyAsync(c->mlp_p, w, sizeof(float) * n, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(c, grim::mlp_pack(c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    c->mlp_set = true;
+    return GRIM_OK;
+}
+
+int grim_mlp_get_weights(grim_ctx_t* c, float* w, size_t n)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!w || n != (size_t)grim::kMlpParams) return fail(c, GRIM_E_INVALID_ARG, "need GRIM_MLP_PARAMS values");
+    if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
+    HIP_TRY(c, hipMemcpyAsync(w, c->mlp_p, sizeof(float) * n, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_mlp_forward(grim_ctx_t* c, const float* X, int64_t n, float* Y)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!X || !Y || n < 0) return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
+    if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
+    HIP_TRY(c, grim::mlp_infer(X, (long)n, c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], Y, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_mlp_backward(grim_ctx_t* c, const float* X, const float* dY, int64_t n, float* dW)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!X || !dY || !dW || n <= 0) return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
+    if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
+    const int chunk = 4096;
+    int rc = ensure_mlp_train_buffers(c, chunk);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemsetAsync(dW, 0, sizeof(float) * grim::kMlpParams, c->st));
+    for (long off = 0; off < n; off += chunk) {
+        const int b = (int)std::min<long>(chunk, n - off);
+        HIP_TRY(c, grim::mlp_batch_grad(c->work, X, nullptr, dY, nullptr, off, b, 0, 0.0f, c->mlp_p, dW,
+                                        off > 0 ? 1 : 0, c->dloss, c->st));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_mlp_train(grim_ctx_t* c, const float* X, const float* T, int64_t n, const grim_train_cfg_t* cfg,
+                   double* loss_hist)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!X || !T || !cfg || n <= 0 || cfg->epochs < 0 || cfg->batch <= 0 || cfg->n_used <= 0 ||
+        cfg->n_used > grim::kMlpOut || !(cfg->lr > 0))
+        return fail(c, GRIM_E_INVALID_ARG, "bad training arguments");
+    if (!c->mlp_set) return fail(c, GRIM_E_STATE, "set initial weights (and normalisation) first");
+    const int B = (int)std::min<int64_t>(cfg->batch, n);
+    int rc = ensure_mlp_train_buffers(c, B);
+    if (rc) return rc;
+    if (c->mlp_idx_cap < n) {
+        if (c->mlp_idx) hipFree(c->mlp_idx);
+        c->mlp_idx = nullptr;
+        rc = dalloc(c, &c->mlp_idx, (size_t)n);
+        if (rc) return rc;
+        c->mlp_idx_cap = n;
+    }
+    HIP_TRY(c, hipMemsetAsync(c->adam_m, 0, sizeof(float) * grim::kMlpTrainable, c->st));
+    HIP_TRY(c, hipMemsetAsync(c->adam_v, 0, sizeof(float) * grim::kMlpTrainable, c->st));
+    std::vector<int> perm((size_t)n);
+    std::mt19937_64 rng(cfg->seed);
+    int step = 0;
+    const long nbatches = n / B;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        for (long i = 0; i < n; ++i) perm[(size_t)i] = (int)i;
+        std::shuffle(perm.begin(), perm.end(), rng);
+        HIP_TRY(c, hipMemcpyAsync(c->mlp_idx, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+        HIP_TRY(c, hipMemsetAsync(c->dloss, 0, sizeof(double), c->st));
+        for (long bi = 0; bi < nbatches; ++bi) {
+            HIP_TRY(c, grim::mlp_batch_grad(c->work, X, T, nullptr, c->mlp_idx, bi * B, B, cfg->n_used,
+                                            1.0f / (float)(B * cfg->n_used), c->mlp_p, c->mlp_grad, 0, c->dloss,
+                                            c->st));
+            HIP_TRY(c, grim::mlp_adam(c->mlp_p, c->mlp_grad, c->adam_m, c->adam_v, grim::kMlpTrainable,
+                                      (float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps, ++step,
+                                      c->st));
+        }
+        double lsum = 0.0;
+        HIP_TRY(c, hipMemcpyAsync(&lsum, c->dloss, sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(c, hipStreamSynchronize(c->st));
+        if (loss_hist) loss_hist[e] = lsum / (double)std::max<long>(nbatches, 1);
+    }
+    HIP_TRY(c, grim::mlp_pack(c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_collect_pairs(grim_ctx_t* c, double dt, int nsteps, int stride, float* X, float* T, int64_t cap,
+                       int64_t* count)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!X || !T || !count || stride < 1 || cap < 0 || nsteps < 0 || !(dt > 0.0))
+        return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
+    int rc = ensure_mlp_zone_buffers(c);
+    if (rc) return rc;
+    Collect col{stride, 0, X, T, (long)cap, 0};
+    for (int s = 0; s < nsteps; ++s) {
+        rc = enqueue_step(c, c->cur, dt, c->st, &col);
+        if (rc) return rc;
+        c->cur = 1 - c->cur;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    *count = std::min<long>(col.count, (long)cap);
     return GRIM_OK;
 }
 

@@ -64,9 +64,8 @@ struct GeoKS {
     __device__ __forceinline__ static constexpr int k7(int m, int n)
     {
         // (0,0)->0 (0,1)->1 (0,3)->2 (1,1)->3 (1,3)->4 (2,2)->5 (3,3)->6
-        return (m > n) ? k7(n, m)
-                       : (m == 0 ? (n == 0 ? 0 : (n == 1 ? 1 : 2))
-                                 : (m == 1 ? (n == 1 ? 3 : 4) : (m == 2 ? 5 : 6)));
+        const int a = m < n ? m : n, b = m < n ? n : m;
+        return a == 0 ? (b == 0 ? 0 : (b == 1 ? 1 : 2)) : (a == 1 ? (b == 1 ? 3 : 4) : (a == 2 ? 5 : 6));
     }
     __device__ __forceinline__ double gcov(int m, int n) const { return c[k7(m, n)]; }
     __device__ __forceinline__ double gcon(int m, int n) const { return u[k7(m, n)]; }

@@ -28,7 +28,7 @@ struct Layout {
 // Device-side accumulators of the solver statistics.
 struct DevStats {
     unsigned long long iters[2];
-    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls;
+    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback;
     unsigned long long max_resid_bits;
     unsigned int max_iters;
     unsigned int pad;
@@ -43,6 +43,26 @@ struct GeoTables {
     const double* face[3];
     const double* conn;
     size_t stride;  // N1 * N2
+};
+
+// Learned-guess network: 32 -> 128 -> 128 -> 16 (FP32 master parameters).
+constexpr int kMlpIn = 32, kMlpHidden = 128, kMlpOut = 16;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHidden;
+constexpr int kOffW2 = kOffB1 + kMlpHidden;
+constexpr int kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kOffW3 = kOffB2 + kMlpHidden;
+constexpr int kOffB3 = kOffW3 + kMlpHidden * kMlpOut;
+constexpr int kOffXm = kOffB3 + kMlpOut;   // input mean      (fixed during training)
+constexpr int kOffXs = kOffXm + kMlpIn;    // input 1/std     (fixed)
+constexpr int kOffYs = kOffXs + kMlpIn;    // output scale    (fixed)
+constexpr int kMlpParams = kOffYs + kMlpOut;
+constexpr int kMlpTrainable = kOffXm;
+
+// FP32 training work buffers for batches of up to `cap` rows.
+struct MlpWork {
+    float *xh, *tb, *z1, *h1, *z2, *h2, *o, *d_o, *dh, *dh1;
+    int cap;
 };
 
 // Per-zone EMHD coefficients frozen at P^E (count and order shared by the
@@ -66,6 +86,7 @@ struct StageArgs {
     double* dbg_divF;
     double* dbg_src;
     double* dbg_sp;
+    float* mlp_x;       // if set: learned-guess input features, [nz][kMlpIn]
 };
 
 struct NewtonArgs {
@@ -78,6 +99,7 @@ struct NewtonArgs {
     uint8_t* flags;
     DevStats* stats;
     int stage;             // 0 or 1 (statistics slot)
+    const float* mlp_y;    // if set: network output per zone [nz][kMlpOut] -> candidate guess
     double tol, eps, eps_bt;
     int k_max, ls_max;
 };
@@ -97,6 +119,17 @@ hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
 hipError_t launch_stream_add(const double* a, const double* b, double* c, size_t n, hipStream_t st);
 hipError_t launch_copy_interior(const Layout& L, int nvar, const double* src, int src_ghosted, double* dst,
                                 int dst_ghosted, hipStream_t st);
+hipError_t launch_collect(const StageArgs& a, int nvar, const double* Pout, int out_ghosted, int stride, int phase,
+                          float* Xo, float* To, long base, long cap, hipStream_t st);
+hipError_t mlp_pack(const float* params, unsigned short* w1t, unsigned short* w2t, unsigned short* w3t,
+                    hipStream_t st);
+hipError_t mlp_infer(const float* X, long n, const float* params, const unsigned short* w1t,
+                     const unsigned short* w2t, const unsigned short* w3t, float* Y, hipStream_t st);
+hipError_t mlp_batch_grad(const MlpWork& w, const float* X, const float* T, const float* dY, const int* idx,
+                          long off, int nbatch, int n_used, float inv_count, const float* p, float* grad, int acc,
+                          double* loss, hipStream_t st);
+hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                    int step, hipStream_t st);
 hipError_t build_geometry(const Layout& L, double spin, double h, double* centre, double* face[3], double* conn,
                           hipStream_t st);
 

@@ -343,6 +343,33 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
 
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.rhs[(long)v * L.nz + z] = rhs[v];
+    if (a.mlp_x) {
+        // learned-guess features (dimensionless): the change of U the stage
+        // asks for, relative to U_rho(P_n); the P_n state; lapse and g^{01},
+        // g^{11} (constant in Minkowski)
+        float x[kMlpIn];
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q) x[q] = 0.0f;
+        const double ur = Un[RHO];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = (float)((rhs[v] * a.dtp - Un[v]) / ur);
+        x[NV] = (float)(Pn[UU] / Pn[RHO]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x[NV + 1 + i] = (float)Pn[U1 + i];
+        const double isr = 1.0 / sqrt(Pn[RHO]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x[NV + 4 + i] = (float)(Pn[B1 + i] * isr);
+        if constexpr (NV == 10) {
+            x[NV + 7] = (float)(Pn[QQ] / Pn[UU]);
+            x[NV + 8] = (float)(Pn[DP] / Pn[UU]);
+        }
+        x[kMlpIn - 3] = (float)g.alpha();
+        x[kMlpIn - 2] = G::nzn(0, 1) ? (float)g.gcon(0, 1) : 0.0f;
+        x[kMlpIn - 1] = (float)g.gcon(1, 1);
+        float* xo = a.mlp_x + z * kMlpIn;
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q) xo[q] = x[q];
+    }
     if (a.dbg_divF) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -421,7 +448,7 @@ __global__ void k_zero_stats(DevStats* s)
 {
     if (threadIdx.x == 0) {
         s->iters[0] = s->iters[1] = 0;
-        s->n_fail = s->n_ls = s->n_unphys = s->zone_stages = s->resid_calls = 0;
+        s->n_fail = s->n_ls = s->n_unphys = s->zone_stages = s->resid_calls = s->n_fallback = 0;
         s->max_resid_bits = 0;
         s->max_iters = 0;
     }
@@ -433,6 +460,42 @@ __global__ __launch_bounds__(kBlock) void k_stream_add(const double* __restrict_
     size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kBlock;
     for (; i < n; i += stride) c[i] = a[i] + b[i];
+}
+
+// Training pairs: for zones z = phase (mod stride), copy the features and
+// write the target (P - P_n) scaled as the guess expects:
+// rho, u relative; utilde absolute; q, DP relative to u_n.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_collect(Layout L, const double* Pn, const double* Pout, int og,
+                                                    const float* X, int stride, int phase, float* Xo, float* To,
+                                                    long base, long cap)
+{
+    const long j = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long z = j * stride + phase;
+    if (z >= L.nz) return;
+    const long idx = base + j;
+    if (idx >= cap) return;
+    const long cell = zone_cell(L, z);
+    double pn[NV], p[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        pn[v] = Pn[(long)v * L.cells + cell];
+        p[v] = og ? Pout[(long)v * L.cells + cell] : Pout[(long)v * L.nz + z];
+    }
+    for (int q = 0; q < kMlpIn; ++q) Xo[idx * kMlpIn + q] = X[z * kMlpIn + q];
+    float t[kMlpOut];
+#pragma unroll
+    for (int q = 0; q < kMlpOut; ++q) t[q] = 0.0f;
+    t[0] = (float)((p[RHO] - pn[RHO]) / pn[RHO]);
+    t[1] = (float)((p[UU] - pn[UU]) / pn[UU]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[2 + i] = (float)(p[U1 + i] - pn[U1 + i]);
+    if constexpr (NV == 10) {
+        t[5] = (float)((p[QQ] - pn[QQ]) / pn[UU]);
+        t[6] = (float)((p[DP] - pn[DP]) / pn[UU]);
+    }
+#pragma unroll
+    for (int q = 0; q < kMlpOut; ++q) To[idx * kMlpOut + q] = t[q];
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_interior(Layout L, int nvar, const double* src, int sg, double* dst,
@@ -571,6 +634,20 @@ hipError_t launch_stream_add(const double* a, const double* b, double* c, size_t
 {
     const long blocks = (long)std::min<size_t>((n + kBlock - 1) / kBlock, (size_t)256 * 64);
     hipLaunchKernelGGL(k_stream_add, dim3((unsigned)std::max<long>(blocks, 1)), dim3(kBlock), 0, st, a, b, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect(const StageArgs& a, int nvar, const double* Pout, int out_ghosted, int stride, int phase,
+                          float* Xo, float* To, long base, long cap, hipStream_t st)
+{
+    const long cnt = phase < a.L.nz ? (a.L.nz - 1 - phase) / stride + 1 : 0;
+    if (cnt <= 0) return hipSuccess;
+    if (nvar == 8)
+        hipLaunchKernelGGL((k_collect<8>), dim3(nblocks(cnt)), dim3(kBlock), 0, st, a.L, a.Pn, Pout, out_ghosted,
+                           a.mlp_x, stride, phase, Xo, To, base, cap);
+    else
+        hipLaunchKernelGGL((k_collect<10>), dim3(nblocks(cnt)), dim3(kBlock), 0, st, a.L, a.Pn, Pout, out_ghosted,
+                           a.mlp_x, stride, phase, Xo, To, base, cap);
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 //   perturbation rule of Sec. 3.1 (a9): column j = (R(P_eps,j) - R(P))/h_j,
 //   h_j = P_eps,j - P_j.  Dense LU with partial pivoting (a10): row swaps are
 //   branch-free selects so J never leaves registers.  Quadratic backtracking
-//   line search (a11, Sec. 3.2).  Converged lanes go idle; the wave leaves
+//   line search (a11, Sec. 3.2), each new lambda kept in [0.1, 0.5] of the
+//   previous one.  Converged lanes go idle; the wave leaves
 //   the loop when every lane has (a12).  Statistics are reduced across the
 //   wave with shuffles and accumulated with one atomic per wave (a13).
 //
@@ -98,13 +99,30 @@ __device__ __forceinline__ unsigned long long wave_maxu64(unsigned long long x)
     return x;
 }
 
+// Candidate guess from the network output y: rho, u relative to P_n,
+// utilde absolute, q and DP relative to u_n; B is set by the caller.
+template <int NV>
+__device__ __forceinline__ void Pc_from_net(const double* pn, const float* y, double* P)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[v] = pn[v];
+    P[RHO] = pn[RHO] * (1.0 + (double)y[0]);
+    P[UU] = pn[UU] * (1.0 + (double)y[1]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[U1 + i] = pn[U1 + i] + (double)y[2 + i];
+    if constexpr (NV == 10) {
+        P[QQ] = pn[QQ] + pn[UU] * (double)y[5];
+        P[DP] = pn[DP] + pn[UU] * (double)y[6];
+    }
+}
+
 template <int NV, class G, typename JT>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
     const long z = (long)blockIdx.x * kWave + threadIdx.x;
     const Layout& L = a.s.L;
     const bool active = z < L.nz;
-    int iters = 0, ncalls = 0;
+    int iters = 0, ncalls = 0, fallback = 0;
     uint8_t fl = 0;
     double rr = 0.0;
 
@@ -113,8 +131,13 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
         ZoneC<NV, G> zc;
         load_zone<NV, G>(a.s, z, cell, zc);
         const Phys& ph = a.s.ph;
+        double P_alt[NV];
 
+        // initial guess: P_n (or the caller's guess) with B at its explicit
+        // update, the exact root of the B rows
+        const double fB = a.s.dtp / zc.g.gdet();
         double P[NV];
+        double nscale;
         {
             double pn[NV];
 #pragma unroll
@@ -122,107 +145,143 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
             St<NV> sn;
             derive<NV>(pn, zc.g, ph, sn);
             // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
-            rr = a.s.dtp / (zc.g.gdet() * pn[RHO] * sn.ucon[0]);
-            if (a.guess) {
+            nscale = a.s.dtp / (zc.g.gdet() * pn[RHO] * sn.ucon[0]);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) P[v] = a.guess[(long)v * L.nz + z];
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) P[v] = pn[v];
+            for (int v = 0; v < NV; ++v) P[v] = a.guess ? a.guess[(long)v * L.nz + z] : pn[v];
+            if (a.mlp_y) {
+                // learned candidate: P = P_n + scaled network output
+                const float* y = a.mlp_y + z * kMlpOut;
+                Pc_from_net<NV>(pn, y, P_alt);
             }
         }
-        const double nscale = rr;
-        // B rows: the explicit update is their exact root
-        {
-            const double f = a.s.dtp / zc.g.gdet();
 #pragma unroll
-            for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * f;
-        }
+        for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * fB;
 
         double R[NV];
         zone_residual<NV, G>(P, zc, ph, R);
         ++ncalls;
         double r = nscale * sqrt(sumsq<NV>(R));
-        const double eps = a.eps;
-        for (;;) {
-            if (!isfinite(r)) { fl |= 16; break; }
-            if (r < a.tol) break;
-            if (iters >= a.k_max) { fl |= 1; break; }
-            // finite-difference Jacobian, column by column
-            JT J[NV][NV];
+        bool from_net = false;
+        if (a.mlp_y) {
+            // keep the learned guess only if its residual is smaller
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                double Pe[NV];
+            for (int i = 0; i < 3; ++i) P_alt[B1 + i] = zc.rhs[B1 + i] * fB;
+            double Rc[NV];
+            zone_residual<NV, G>(P_alt, zc, ph, Rc);
+            ++ncalls;
+            const double rc = nscale * sqrt(sumsq<NV>(Rc));
+            if (rc < r) {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) Pe[q] = P[q];
-                const double pj = P[j];
-                const bool small = fabs(pj) < 5.0 * eps;
-                double pe = small ? eps : (1.0 + eps) * pj;
-                double h = pe - pj;
-                if (h == 0.0) {
-                    pe = pj + eps;
-                    h = pe - pj;
+                for (int v = 0; v < NV; ++v) {
+                    P[v] = P_alt[v];
+                    R[v] = Rc[v];
                 }
-                Pe[j] = pe;
-                double Re[NV];
-                zone_residual<NV, G>(Pe, zc, ph, Re);
-                ++ncalls;
-                const double ih = 1.0 / h;
-#pragma unroll
-                for (int i = 0; i < NV; ++i) J[i][j] = (JT)((Re[i] - R[i]) * ih);
+                r = rc;
+                from_net = true;
+            } else {
+                fallback = 1;
             }
-            JT x[NV];
+        }
+        const double eps = a.eps;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            fl = 0;
+            int k = 0;
+            for (;;) {
+                if (!isfinite(r)) { fl |= 16; break; }
+                if (r < a.tol) break;
+                if (k >= a.k_max) { fl |= 1; break; }
+                // finite-difference Jacobian, column by column
+                JT J[NV][NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) x[v] = (JT)(-R[v]);
-            if (!lu_solve<NV, JT>(J, x)) { fl |= 4; break; }
-            double dP[NV];
+                for (int j = 0; j < NV; ++j) {
+                    double Pe[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) dP[v] = (double)x[v];
-
-            // quadratic backtracking line search
-            const double f0 = r * r;
-            double lam = 1.0;
-            bool accepted = false, have = false;
-            double Pf[NV], Rf[NV], rf = 0.0;
-            for (int t = 0; t < a.ls_max; ++t) {
-                double Pt[NV], Rt[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], P[v]);
-                zone_residual<NV, G>(Pt, zc, ph, Rt);
-                ++ncalls;
-                const double rt = nscale * sqrt(sumsq<NV>(Rt));
-                if (isfinite(rt)) {
-                    have = true;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        Pf[v] = Pt[v];
-                        Rf[v] = Rt[v];
+                    for (int q = 0; q < NV; ++q) Pe[q] = P[q];
+                    const double pj = P[j];
+                    const bool small = fabs(pj) < 5.0 * eps;
+                    double pe = small ? eps : (1.0 + eps) * pj;
+                    double h = pe - pj;
+                    if (h == 0.0) {
+                        pe = pj + eps;
+                        h = pe - pj;
                     }
-                    rf = rt;
-                    if (rt < r * (1.0 - a.eps_bt * lam)) {
-                        accepted = true;
+                    Pe[j] = pe;
+                    double Re[NV];
+                    zone_residual<NV, G>(Pe, zc, ph, Re);
+                    ++ncalls;
+                    const double ih = 1.0 / h;
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) J[i][j] = (JT)((Re[i] - R[i]) * ih);
+                }
+                JT x[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) x[v] = (JT)(-R[v]);
+                if (!lu_solve<NV, JT>(J, x)) { fl |= 4; break; }
+                double dP[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) dP[v] = (double)x[v];
+
+                // quadratic backtracking line search
+                const double f0 = r * r;
+                double lam = 1.0;
+                bool accepted = false, have = false;
+                double Pf[NV], Rf[NV], rf = 0.0;
+                for (int t = 0; t < a.ls_max; ++t) {
+                    double Pt[NV], Rt[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], P[v]);
+                    zone_residual<NV, G>(Pt, zc, ph, Rt);
+                    ++ncalls;
+                    const double rt = nscale * sqrt(sumsq<NV>(Rt));
+                    if (isfinite(rt)) {
+                        have = true;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            Pf[v] = Pt[v];
+                            Rf[v] = Rt[v];
+                        }
+                        rf = rt;
+                        if (rt < r * (1.0 - a.eps_bt * lam)) {
+                            accepted = true;
+                            break;
+                        }
+                        // minimiser of the quadratic model f(0) - 2 f(0) lam + c lam^2,
+                        // kept within [0.1, 0.5] of the previous lambda
+                        const double ln = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
+                        lam = fmin(fmax(ln, 0.1 * lam), 0.5 * lam);
+                    } else {
+                        lam *= 0.5;
+                    }
+                }
+                if (!accepted) {
+                    fl |= 2;
+                    if (!have) {
+                        fl |= 16;
+                        ++iters;
+                        ++k;
                         break;
                     }
-                    lam = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
-                } else {
-                    lam *= 0.5;
                 }
-            }
-            if (!accepted) {
-                fl |= 2;
-                if (!have) {
-                    fl |= 16;
-                    ++iters;
-                    break;
-                }
-            }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                P[v] = Pf[v];
-                R[v] = Rf[v];
+                for (int v = 0; v < NV; ++v) {
+                    P[v] = Pf[v];
+                    R[v] = Rf[v];
+                }
+                r = rf;
+                ++iters;
+                ++k;
             }
-            r = rf;
-            ++iters;
+            if (!(from_net && (fl & (1 | 4 | 16)))) break;
+            // the solve from the learned guess failed: start again from P_n
+            from_net = false;
+            fallback = 1;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P[v] = a.s.Pn[(long)v * L.cells + cell];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * fB;
+            zone_residual<NV, G>(P, zc, ph, R);
+            ++ncalls;
+            r = nscale * sqrt(sumsq<NV>(R));
         }
         rr = r;
         if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= 8;
@@ -254,6 +313,7 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
         const double nu = wave_sum(active && (fl & 8) ? 1.0 : 0.0);
         const double na = wave_sum(active ? 1.0 : 0.0);
         const double nc = wave_sum(active ? (double)ncalls : 0.0);
+        const double nfb = wave_sum(active ? (double)fallback : 0.0);
         unsigned long long rb = 0;
         if (active) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
         rb = wave_maxu64(rb);
@@ -265,6 +325,7 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
             if (nu > 0) atomicAdd(&a.stats->n_unphys, (unsigned long long)nu);
             atomicAdd(&a.stats->zone_stages, (unsigned long long)na);
             atomicAdd(&a.stats->resid_calls, (unsigned long long)nc);
+            if (nfb > 0) atomicAdd(&a.stats->n_fallback, (unsigned long long)nfb);
             atomicMax(&a.stats->max_resid_bits, rb);
         }
     }

@@ -20,6 +20,8 @@ GRIM_IDEAL_MHD, GRIM_EMHD = 8, 10
 GRIM_MINKOWSKI, GRIM_MKS_KERR = 0, 1
 GRIM_BC = {"periodic": 0, "outflow": 1, "polar": 2}
 GRIM_JAC = {"f64": 0, "f32": 1}
+GRIM_GUESS = {"pn": 0, "mlp": 1}
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 32, 128, 16, 22880
 FLAGS = {"NOT_CONVERGED": 1, "LS_EXHAUSTED": 2, "SINGULAR": 4, "UNPHYSICAL": 8, "NONFINITE": 16}
 
 
@@ -34,7 +36,7 @@ class grim_config_t(C.Structure):
         ("plm_theta", C.c_double),
         ("tol", C.c_double), ("eps_fd", C.c_double), ("eps_bt", C.c_double),
         ("k_max", C.c_int), ("ls_max", C.c_int),
-        ("jac_precision", C.c_int),
+        ("jac_precision", C.c_int), ("guess", C.c_int),
         ("floors", C.c_int), ("rho_floor", C.c_double), ("u_floor", C.c_double),
     ]
 
@@ -44,6 +46,7 @@ class grim_stats_t(C.Structure):
         ("mean_iters", C.c_double * 2), ("max_iters", C.c_int32), ("pad", C.c_int32),
         ("n_fail", C.c_int64), ("n_ls_exhausted", C.c_int64), ("n_unphysical", C.c_int64),
         ("max_resid", C.c_double), ("zone_stages", C.c_int64), ("n_resid_calls", C.c_int64),
+        ("n_fallback", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -56,7 +59,14 @@ class grim_stats_t(C.Structure):
             "max_resid": float(self.max_resid),
             "zone_stages": int(self.zone_stages),
             "n_resid_calls": int(self.n_resid_calls),
+            "n_fallback": int(self.n_fallback),
         }
+
+
+class grim_train_cfg_t(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("n_used", C.c_int), ("pad", C.c_int),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 _VP = C.c_void_p
@@ -94,6 +104,12 @@ def load():
     L.grim_stream_add.argtypes = [_VP, _VP, _VP, _VP, C.c_size_t]
     L.grim_profile.argtypes = [_VP, C.c_int]
     L.grim_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    L.grim_mlp_set_weights.argtypes = [_VP, _VP, C.c_size_t]
+    L.grim_mlp_get_weights.argtypes = [_VP, _VP, C.c_size_t]
+    L.grim_mlp_forward.argtypes = [_VP, _VP, C.c_int64, _VP]
+    L.grim_mlp_backward.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+    L.grim_mlp_train.argtypes = [_VP, _VP, _VP, C.c_int64, C.POINTER(grim_train_cfg_t), _VP]
+    L.grim_collect_pairs.argtypes = [_VP, _D, C.c_int, C.c_int, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -101,7 +117,9 @@ def load():
 def exported_symbols():
     return ["grim_create", "grim_destroy", "grim_last_error", "grim_last_global_error", "grim_device_bytes",
             "grim_set_prims", "grim_get_prims", "grim_cfl_dt", "grim_run", "grim_residual", "grim_stage_solve",
-            "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_profile", "grim_kernel_times"]
+            "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_profile", "grim_kernel_times",
+            "grim_mlp_set_weights", "grim_mlp_get_weights", "grim_mlp_forward", "grim_mlp_backward",
+            "grim_mlp_train", "grim_collect_pairs"]
 
 
 def _ptr(x):
@@ -148,6 +166,7 @@ def config_from_workload(wl: dict) -> grim_config_t:
     c.k_max = wl.get("k_max", 20)
     c.ls_max = wl.get("ls_max", 10)
     c.jac_precision = GRIM_JAC[wl.get("jac", "f64")]
+    c.guess = GRIM_GUESS[wl.get("guess", "pn")]
     c.floors = 1 if wl.get("floors", False) else 0
     c.rho_floor = wl.get("rho_floor", 1e-5)
     c.u_floor = wl.get("u_floor", 1e-7)
@@ -210,7 +229,7 @@ def grim_stream_add(ctx, a, b, c, n):
     _check(ctx, load().grim_stream_add(ctx, _ptr(a), _ptr(b), _ptr(c), int(n)), "grim_stream_add")
 
 
-KERNEL_GROUPS = ["ghost_fill", "face_flux", "flux_ct_emf", "stage_rhs", "newton"]
+KERNEL_GROUPS = ["ghost_fill", "face_flux", "flux_ct_emf", "stage_rhs", "newton", "mlp_infer"]
 
 
 def grim_profile(ctx, enable):
@@ -218,10 +237,46 @@ def grim_profile(ctx, enable):
 
 
 def grim_kernel_times(ctx):
-    ms = (C.c_double * 5)()
-    n = (C.c_int64 * 5)()
-    _check(ctx, load().grim_kernel_times(ctx, ms, n, 5), "grim_kernel_times")
-    return {KERNEL_GROUPS[i]: (float(ms[i]), int(n[i])) for i in range(5)}
+    k = len(KERNEL_GROUPS)
+    ms = (C.c_double * k)()
+    n = (C.c_int64 * k)()
+    _check(ctx, load().grim_kernel_times(ctx, ms, n, k), "grim_kernel_times")
+    return {KERNEL_GROUPS[i]: (float(ms[i]), int(n[i])) for i in range(k)}
+
+
+def grim_mlp_set_weights(ctx, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(ctx, load().grim_mlp_set_weights(ctx, w.ctypes.data, w.size), "grim_mlp_set_weights")
+
+
+def grim_mlp_get_weights(ctx):
+    w = np.empty(MLP_PARAMS, dtype=np.float32)
+    _check(ctx, load().grim_mlp_get_weights(ctx, w.ctypes.data, w.size), "grim_mlp_get_weights")
+    return w
+
+
+def grim_mlp_forward(ctx, X, n, Y):
+    _check(ctx, load().grim_mlp_forward(ctx, _ptr(X), int(n), _ptr(Y)), "grim_mlp_forward")
+
+
+def grim_mlp_backward(ctx, X, dY, n, dW):
+    _check(ctx, load().grim_mlp_backward(ctx, _ptr(X), _ptr(dY), int(n), _ptr(dW)), "grim_mlp_backward")
+
+
+def grim_mlp_train(ctx, X, T, n, epochs, batch, n_used, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+    cfg = grim_train_cfg_t(epochs=epochs, batch=batch, n_used=n_used, pad=0, lr=lr, beta1=beta1, beta2=beta2,
+                           eps=eps, seed=seed)
+    hist = np.zeros(max(epochs, 1))
+    _check(ctx, load().grim_mlp_train(ctx, _ptr(X), _ptr(T), int(n), C.byref(cfg), hist.ctypes.data),
+           "grim_mlp_train")
+    return hist[:epochs]
+
+
+def grim_collect_pairs(ctx, dt, nsteps, stride, X, T, cap):
+    cnt = C.c_int64()
+    _check(ctx, load().grim_collect_pairs(ctx, dt, int(nsteps), int(stride), _ptr(X), _ptr(T), int(cap),
+                                          C.byref(cnt)), "grim_collect_pairs")
+    return int(cnt.value)
 
 
 def grim_device_bytes(ctx):

@@ -1,0 +1,84 @@
+"""Training set-up of the learned initial guess (argument marshalling and
+bookkeeping only; every pair, gradient and update is computed by libgrim).
+
+Pairs come from the plain FP64 solver on training seeds; the input and output
+normalisation are the pairs' mean / standard deviation; the weights start
+from a seeded He initialisation; training is Adam on the GPU.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import grim
+from . import workloads as W
+
+N_USED = {8: 5, 10: 7}
+
+
+def collect(wl: dict, seeds, steps: int, stride: int, cap: int):
+    """(X, T) device tensors of training pairs from FP64 runs of wl on seeds."""
+    import torch
+
+    X = torch.empty((cap, grim.MLP_IN), dtype=torch.float32, device="cuda")
+    T = torch.empty((cap, grim.MLP_OUT), dtype=torch.float32, device="cuda")
+    n = 0
+    for seed in seeds:
+        ctx = grim.Context(dict(wl, guess="pn"))
+        P0 = W.initial_state(wl, seed=seed)
+        ctx.set_prims(P0)
+        dt = ctx.cfl_dt(wl["cfl"])
+        got = grim.grim_collect_pairs(ctx.ctx, dt, steps, stride, X[n:], T[n:], cap - n)
+        ctx.close()
+        n += got
+        if n >= cap:
+            break
+    return X[:n], T[:n]
+
+
+def normalisation(X, T, n_used: int):
+    """Input mean and 1/std (0 for constant inputs), output std (1 if unused)."""
+    x = X.double()
+    xm = x.mean(dim=0)
+    xs = x.std(dim=0)
+    istd = np.where(xs.cpu().numpy() > 0, 1.0 / np.maximum(xs.cpu().numpy(), 1e-300), 0.0)
+    ys = np.ones(grim.MLP_OUT)
+    t = T.double()[:, :n_used].std(dim=0).cpu().numpy()
+    ys[:n_used] = np.where(t > 0, t, 1.0)
+    return xm.cpu().numpy(), istd, ys
+
+
+def he_init(seed: int, x_mean, x_istd, y_scale):
+    rng = np.random.default_rng(seed)
+    parts = [
+        rng.normal(0.0, np.sqrt(2.0 / grim.MLP_IN), (grim.MLP_IN, grim.MLP_HIDDEN)).ravel(),
+        np.zeros(grim.MLP_HIDDEN),
+        rng.normal(0.0, np.sqrt(2.0 / grim.MLP_HIDDEN), (grim.MLP_HIDDEN, grim.MLP_HIDDEN)).ravel(),
+        np.zeros(grim.MLP_HIDDEN),
+        rng.normal(0.0, np.sqrt(1.0 / grim.MLP_HIDDEN), (grim.MLP_HIDDEN, grim.MLP_OUT)).ravel(),
+        np.zeros(grim.MLP_OUT),
+        np.asarray(x_mean, dtype=np.float64), np.asarray(x_istd, dtype=np.float64),
+        np.asarray(y_scale, dtype=np.float64),
+    ]
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == grim.MLP_PARAMS
+    return w
+
+
+def train_guess(wl: dict, seeds=(1, 2, 3, 4), steps: int = None, pairs: int = 1_000_000, epochs: int = 8,
+                batch: int = 4096, lr: float = 2e-3, init_seed: int = 0):
+    """Collect ~`pairs` training pairs from FP64 runs on `seeds` and train the
+    network on the GPU.  Returns (weights, info)."""
+    steps = wl["steps"] if steps is None else steps
+    zones = int(np.prod(wl["n"]))
+    candidates = len(seeds) * steps * 2 * zones
+    stride = max(1, candidates // pairs)
+    X, T = collect(wl, seeds, steps, stride, pairs)
+    n_used = N_USED[wl["nvar"]]
+    xm, xs, ys = normalisation(X, T, n_used)
+    w0 = he_init(init_seed, xm, xs, ys)
+    ctx = grim.Context(dict(wl, guess="pn"))
+    grim.grim_mlp_set_weights(ctx.ctx, w0)
+    hist = grim.grim_mlp_train(ctx.ctx, X, T, X.shape[0], epochs, batch, n_used, lr=lr, seed=init_seed)
+    w = grim.grim_mlp_get_weights(ctx.ctx)
+    ctx.close()
+    return w, {"pairs": int(X.shape[0]), "stride": stride, "loss": [float(v) for v in hist], "n_used": n_used}

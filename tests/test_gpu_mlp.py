@@ -1,0 +1,126 @@
+"""GPU checks of the learned guess through the C ABI: BF16 MFMA inference and
+FP32 gradients against the FP64 numpy oracle, training, and the guess inside
+the Newton solve (with its fallback)."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_1702_01106_amd import workloads as W
+from tests.helpers import prim_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    return M.init_params(seed, x_mean=rng.normal(0, 0.5, M.D_IN), x_istd=rng.uniform(0.5, 2.0, M.D_IN),
+                         y_scale=rng.uniform(0.5, 2.0, M.D_OUT))
+
+
+def _ctx():
+    from paper_1702_01106_amd import grim
+
+    return grim, grim.Context(W.small("emhd2d_modes_256", [16, 16]))
+
+
+def test_forward_bf16_matches_oracle(torch_cuda):
+    grim, g = _ctx()
+    th = _params(1)
+    grim.grim_mlp_set_weights(g.ctx, th.astype(np.float32))
+    rng = np.random.default_rng(2)
+    n = 1000  # not a multiple of the 128-row tile
+    X = rng.normal(0, 1, (n, M.D_IN)).astype(np.float32)
+    Xd = torch_cuda.from_numpy(X).cuda()
+    Y = torch_cuda.empty((n, M.D_OUT), dtype=torch_cuda.float32, device="cuda")
+    grim.grim_mlp_forward(g.ctx, Xd, n, Y)
+    y = Y.cpu().numpy().astype(np.float64)
+    ref = M.forward(th.astype(np.float32).astype(np.float64), X.astype(np.float64), bf16_inference=True)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 1e-2 * scale, np.abs(y - ref).max() / scale
+    assert np.abs(y - ref).mean() <= 2e-3 * scale
+    full = M.forward(th.astype(np.float32).astype(np.float64), X.astype(np.float64))
+    assert np.abs(y - full).max() <= 5e-2 * scale
+
+
+def test_backward_matches_oracle(torch_cuda):
+    grim, g = _ctx()
+    th = _params(3).astype(np.float32)
+    grim.grim_mlp_set_weights(g.ctx, th)
+    rng = np.random.default_rng(4)
+    n = 700
+    X = rng.normal(0, 1, (n, M.D_IN)).astype(np.float32)
+    dY = rng.normal(0, 1, (n, M.D_OUT)).astype(np.float32)
+    dW = torch_cuda.empty(M.N_PARAMS, dtype=torch_cuda.float32, device="cuda")
+    grim.grim_mlp_backward(g.ctx, torch_cuda.from_numpy(X).cuda(), torch_cuda.from_numpy(dY).cuda(), n, dW)
+    gpu = dW.cpu().numpy().astype(np.float64)
+    ref = M.backward(th.astype(np.float64), X.astype(np.float64), dY.astype(np.float64))
+    for name, shape in M.SHAPES:
+        pass
+    assert np.linalg.norm(gpu - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert np.all(gpu[M.N_PARAMS - 80:] == 0.0)
+
+
+def test_training_reduces_loss(torch_cuda):
+    """Adam on a smooth synthetic regression: the epoch loss falls by 10x and
+    the oracle's loss at the trained weights matches the last epoch."""
+    grim, g = _ctx()
+    rng = np.random.default_rng(5)
+    n = 16384
+    X = rng.normal(0, 1, (n, M.D_IN)).astype(np.float32)
+    A = rng.normal(0, 0.3, (M.D_IN, 7))
+    T = np.zeros((n, M.D_OUT), dtype=np.float32)
+    T[:, :7] = np.tanh(X @ A)
+    th = M.init_params(6, x_mean=np.zeros(M.D_IN), x_istd=np.ones(M.D_IN),
+                       y_scale=np.concatenate([T[:, :7].std(axis=0), np.ones(9)]))
+    grim.grim_mlp_set_weights(g.ctx, th.astype(np.float32))
+    Xd, Td = torch_cuda.from_numpy(X).cuda(), torch_cuda.from_numpy(T).cuda()
+    hist = grim.grim_mlp_train(g.ctx, Xd, Td, n, 10, 512, 7, lr=2e-3, seed=1)
+    assert hist[-1] < 0.1 * hist[0], hist
+    w = grim.grim_mlp_get_weights(g.ctx).astype(np.float64)
+    ref = M.mse_loss(w, X[:4096].astype(np.float64), T[:4096].astype(np.float64), 7)
+    assert ref < 2.0 * hist[-1] + 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_learned_guess_in_the_solver(torch_cuda):
+    """Pairs from FP64 runs on seeds 1-2, trained on the GPU, then seed 0: the
+    learned guess cuts the mean Newton iterations and the result agrees with the
+    plain solve; a network scaled by 1e3 is rejected everywhere (fallback) and
+    gives the plain result bit for bit."""
+    from paper_1702_01106_amd import grim, learned
+
+    wl = W.small("emhd2d_modes_256", [128, 128])
+    w, info = learned.train_guess(wl, seeds=(1, 2), steps=20, pairs=200_000, epochs=6, batch=2048)
+    assert info["loss"][-1] < info["loss"][0]
+    P0 = W.initial_state(wl, seed=0)
+    plain = grim.Context(wl)
+    plain.set_prims(P0)
+    dt = plain.cfl_dt(wl["cfl"])
+    st0 = plain.run(dt, 10)
+    ref = plain.get_prims()
+    net = grim.Context(dict(wl, guess="mlp"))
+    grim.grim_mlp_set_weights(net.ctx, w)
+    net.set_prims(P0)
+    st1 = net.run(dt, 10)
+    got = net.get_prims()
+    assert st1["n_fail"] == 0 and st1["max_resid"] < wl["tol"]
+    assert prim_rel_err(got, ref).max() < 1e-6
+    it0, it1 = sum(st0["mean_iters"]), sum(st1["mean_iters"])
+    print("mean iters plain", st0["mean_iters"], "learned", st1["mean_iters"], "fallback", st1["n_fallback"])
+    assert it1 < 0.9 * it0, (st0["mean_iters"], st1["mean_iters"])
+    bad = w.copy()
+    bad[: M.N_PARAMS - 80] *= 1e3
+    junk = grim.Context(dict(wl, guess="mlp"))
+    grim.grim_mlp_set_weights(junk.ctx, bad)
+    junk.set_prims(P0)
+    st2 = junk.run(dt, 10)
+    assert st2["n_fallback"] >= 0.99 * st2["zone_stages"]
+    assert np.array_equal(junk.get_prims(), ref)

@@ -256,9 +256,12 @@ def test_newton_generic_behaviour(oracle_mod):
     # arctan: plain Newton diverges from |x0| > 1.39; backtracking converges
     x, it, rr, fl = O.newton(lambda x: np.arctan(x), np.array([3.0]))
     assert fl == 0 and abs(x[0]) < 1e-10 and rr < 1e-10
-    # no real root: never converges
+    # far start on a saturating residual: several rejected trials per step
+    x, it, rr, fl = O.newton(lambda x: np.arctan(x), np.array([20.0]))
+    assert fl == 0 and abs(x[0]) < 1e-10 and it <= 20
+    # no real root: never reports convergence
     x, it, rr, fl = O.newton(lambda x: x * x + 1.0, np.array([0.5]), k_max=6)
-    assert fl & oracle_mod.FLAGS["NOT_CONVERGED"] and it == 6
+    assert fl & (oracle_mod.FLAGS["NOT_CONVERGED"] | oracle_mod.FLAGS["SINGULAR"]) and rr > 1e-10
     # singular Jacobian (second residual independent of x)
     x, it, rr, fl = O.newton(lambda x: np.array([x[0] - 1.0, 1.0 + 0 * x[1]]), np.array([0.0, 0.0]))
     assert fl & oracle_mod.FLAGS["SINGULAR"] and it == 0
