@@ -121,10 +121,15 @@ def stream_probe(grim, wl, n: int = 1 << 26, reps: int = 20) -> dict:
     return {"gbs": 3 * 8 * n * reps / t / 1e9, "bytes_per_launch": 3 * 8 * n, "exact": ok}
 
 
-def timed_run(grim, W, wl, P0, steps, warmup):
+def timed_run(grim, W, wl, P0, steps, warmup, weights=None):
+    """Graph-replayed timed run, then an instrumented eager pass over the same
+    steps (per-kernel device time).  Returns dt, seconds, stats of both runs,
+    kernel times and the final primitives of the timed run."""
     import torch
 
     ctx = grim.Context(wl)
+    if weights is not None:
+        grim.grim_mlp_set_weights(ctx.ctx, weights)
     ctx.set_prims(P0)
     dt = ctx.cfl_dt(wl["cfl"])
     if warmup > 0:
@@ -135,6 +140,7 @@ def timed_run(grim, W, wl, P0, steps, warmup):
     st = ctx.run(dt, steps, use_graph=True, want_stats=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    P_end = ctx.get_prims()
     # instrumented eager pass over the same steps: per-kernel device time
     ctx.set_prims(P0)
     ctx.profile(True)
@@ -142,7 +148,44 @@ def timed_run(grim, W, wl, P0, steps, warmup):
     times = ctx.kernel_times()
     ctx.profile(False)
     ctx.close()
-    return dt, t, st, st_p, times
+    return dt, t, st, st_p, times, P_end
+
+
+FAMILIES = [[0], [1], [2, 3, 4], [5, 6, 7], [8], [9]]
+
+
+def max_rel_diff(A, B):
+    """Largest |A - B| per primitive over max(|B_v|, RMS of B over v's family)."""
+    import numpy as np
+
+    worst = 0.0
+    for fam in FAMILIES:
+        fam = [v for v in fam if v < B.shape[0]]
+        if not fam:
+            continue
+        rms = float(np.sqrt(np.mean(np.stack([B[v] ** 2 for v in fam]))))
+        for v in fam:
+            den = np.maximum(np.abs(B[v]), rms)
+            den = np.where(den > 0, den, 1.0)
+            worst = max(worst, float((np.abs(A[v] - B[v]) / den).max()))
+    return worst
+
+
+def variant_line(zones, steps, t, st, times, P_end, P_ref, value_ref):
+    v = zones * steps / t
+    return {
+        "value": v,
+        "ms_per_step": t / steps * 1e3,
+        "mean_newton_iters": st["mean_iters"],
+        "max_resid": st["max_resid"],
+        "n_fail": st["n_fail"],
+        "n_fallback": st.get("n_fallback", 0),
+        "n_f64_retry": st.get("n_f64_retry", 0),
+        "newton_avg_launch_us": times["newton"][0] / max(times["newton"][1], 1) * 1e3,
+        "kernel_ms": {k: x[0] for k, x in times.items()},
+        "max_rel_diff_vs_f64_gpu": max_rel_diff(P_end, P_ref),
+        "speedup_vs_f64": v / value_ref,
+    }
 
 
 def main() -> int:
@@ -154,6 +197,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--pairs", type=int, default=1_000_000, help="training pairs of the learned guess")
+    ap.add_argument("--epochs", type=int, default=8, help="training epochs of the learned guess")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU halo exchange is not built",
@@ -174,7 +219,7 @@ def main() -> int:
     zones = int(P0[0].size)
     nvar = wl["nvar"]
 
-    dt, t, st, st_p, times = timed_run(grim, W, wl, P0, args.steps, args.warmup)
+    dt, t, st, st_p, times, P_f64 = timed_run(grim, W, wl, P0, args.steps, args.warmup)
     value = zones * args.steps / t
     ms_newton, n_newton = times["newton"]
     flops = newton_flops(nvar, st_p["zone_stages"], (st_p["mean_iters"][0] + st_p["mean_iters"][1]) * zones
@@ -216,19 +261,24 @@ def main() -> int:
     }
     out["stream"] = stream_probe(grim, wl)
     if not args.no_variants:
-        wl32 = dict(wl, jac="f32")
-        _, t32, st32, _, times32 = timed_run(grim, W, wl32, P0, args.steps, args.warmup)
-        out["variants"] = {
-            "f32_jacobian_lu": {
-                "value": zones * args.steps / t32,
-                "ms_per_step": t32 / args.steps * 1e3,
-                "mean_newton_iters": st32["mean_iters"],
-                "max_resid": st32["max_resid"],
-                "n_fail": st32["n_fail"],
-                "newton_avg_launch_us": times32["newton"][0] / max(times32["newton"][1], 1) * 1e3,
-                "speedup_vs_f64": (zones * args.steps / t32) / value,
-            }
-        }
+        from paper_1702_01106_amd import learned
+
+        variants = {}
+        r = timed_run(grim, W, dict(wl, jac="f32"), P0, args.steps, args.warmup)
+        variants["f32_jacobian_lu"] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_f64, value)
+        # learned guess: trained once on pairs from FP64 runs of the same
+        # workload on seeds 1-4 (untimed), evaluated on seed 0
+        t0 = time.perf_counter()
+        w, info = learned.train_guess(wl, seeds=(1, 2, 3, 4), steps=wl["steps"], pairs=args.pairs,
+                                      epochs=args.epochs, batch=4096)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        for name, jac in (("learned_guess_f64", "f64"), ("learned_guess_f32_jacobian", "f32")):
+            r = timed_run(grim, W, dict(wl, jac=jac, guess="mlp"), P0, args.steps, args.warmup, weights=w)
+            variants[name] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_f64, value)
+        variants["training"] = {"pairs": info["pairs"], "epochs": args.epochs, "seconds": t_train,
+                                "loss_first_last": [info["loss"][0], info["loss"][-1]], "seeds": [1, 2, 3, 4]}
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, P0, dt, args.cpu_steps)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

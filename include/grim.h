@@ -75,6 +75,9 @@ extern "C" {
 #define GRIM_FLAG_SINGULAR 4
 #define GRIM_FLAG_UNPHYSICAL 8
 #define GRIM_FLAG_NONFINITE 16
+/* the FP32-Jacobian solve failed in this zone, which was then solved again
+ * from P_n with the FP64 Jacobian (the other bits are that solve's) */
+#define GRIM_FLAG_F64_RETRY 32
 
 typedef struct grim_ctx grim_ctx_t;
 
@@ -99,7 +102,9 @@ typedef struct {
     double eps_bt;       /* line-search acceptance parameter (Sec. 3.2)      */
     int k_max;           /* maximum Newton iterations                        */
     int ls_max;          /* maximum line-search trials per iteration         */
-    int jac_precision;   /* GRIM_JAC_F64 or GRIM_JAC_F32                     */
+    int jac_precision;   /* GRIM_JAC_F64 or GRIM_JAC_F32; with F32, zones whose
+                            solve fails are solved again with F64 (flag
+                            GRIM_FLAG_F64_RETRY, stats.n_f64_retry)          */
     int guess;           /* GRIM_GUESS_PN or GRIM_GUESS_MLP                  */
     int floors;          /* 1: rho >= rho_floor r^-3/2, u >= u_floor r^-5/2   */
     double rho_floor, u_floor;
@@ -117,6 +122,7 @@ typedef struct {
     int64_t zone_stages;    /* zones x stages accumulated                    */
     int64_t n_resid_calls;  /* residual evaluations R(P), summed over zones  */
     int64_t n_fallback;     /* zones whose learned guess was rejected        */
+    int64_t n_f64_retry;    /* zones solved again with the FP64 Jacobian     */
 } grim_stats_t;
 
 /* Adam training of the learned-guess network. */

@@ -156,21 +156,28 @@ static void o_geom(const ocfg_t* c, const double X[4], ogeom_t* G)
 }
 
 /* Christoffel symbols conn[l][a][b] = Gamma^l_{ab}
- * = 1/2 g^{lk} (d_a g_kb + d_b g_ka - d_k g_ab), with the metric derivatives
- * taken by central differences of step 1e-5 in X. */
+ * = 1/2 g^{lk} (d_a g_kb + d_b g_ka - d_k g_ab).  Reading: the paper does not
+ * say how the metric is differentiated; here each d_k g_ab is the
+ * fourth-order central difference with step 1e-3 in X^k,
+ *   (8 (g(X+h) - g(X-h)) - (g(X+2h) - g(X-2h))) / (12 h),
+ * whose truncation (~h^4) and rounding (~eps/h) errors are both ~1e-12
+ * relative here. */
 static void o_conn(const ocfg_t* c, const double X[4], double conn[4][4][4])
 {
-    const double del = 1e-5;
+    const double del = 1e-3;
     double dg[4][4][4]; /* dg[k][a][b] = d_k g_ab */
     for (int k = 0; k < 4; ++k) {
-        double Xp[4], Xm[4], gp[4][4], gm[4][4];
-        for (int m = 0; m < 4; ++m) { Xp[m] = X[m]; Xm[m] = X[m]; }
-        Xp[k] += del;
-        Xm[k] -= del;
-        o_metric_cov(c, Xp, gp);
-        o_metric_cov(c, Xm, gm);
+        double g[4][4][4]; /* metric at X + s del e_k, s = -2, -1, 1, 2 */
+        const int sh[4] = {-2, -1, 1, 2};
+        for (int q = 0; q < 4; ++q) {
+            double Xs[4];
+            for (int m = 0; m < 4; ++m) Xs[m] = X[m];
+            Xs[k] += sh[q] * del;
+            o_metric_cov(c, Xs, g[q]);
+        }
         for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) dg[k][a][b] = (gp[a][b] - gm[a][b]) / (2.0 * del);
+            for (int b = 0; b < 4; ++b)
+                dg[k][a][b] = (8.0 * (g[2][a][b] - g[1][a][b]) - (g[3][a][b] - g[0][a][b])) / (12.0 * del);
     }
     ogeom_t G;
     o_geom(c, X, &G);

@@ -96,19 +96,26 @@ def backward(theta, X, dY):
     return pack(g)
 
 
+def _inv(ys):
+    """1 / y_scale, with 0 for outputs whose scale is 0 (held at zero, no loss)."""
+    ys = np.asarray(ys, dtype=np.float64)
+    return np.where(ys != 0.0, 1.0 / np.where(ys != 0.0, ys, 1.0), 0.0)
+
+
 def mse_loss(theta, X, T, n_used: int):
-    """Mean over rows and the first n_used outputs of ((y - t) / y_scale)^2."""
-    ys = unpack(theta)["y_scale"]
+    """Mean over rows and the first n_used outputs of ((y - t) / y_scale)^2;
+    outputs with y_scale 0 contribute 0 (they still count in the mean)."""
+    iys = _inv(unpack(theta)["y_scale"])
     y = forward(theta, X)
-    d = ((y - T) / ys)[:, :n_used]
+    d = ((y - T) * iys)[:, :n_used]
     return float(np.mean(d * d))
 
 
 def mse_grad(theta, X, T, n_used: int):
-    ys = unpack(theta)["y_scale"]
+    iys = _inv(unpack(theta)["y_scale"])
     y = forward(theta, X)
     dY = np.zeros_like(y)
-    dY[:, :n_used] = 2.0 * ((y - T) / ys ** 2)[:, :n_used] / (y.shape[0] * n_used)
+    dY[:, :n_used] = 2.0 * ((y - T) * iys * iys)[:, :n_used] / (y.shape[0] * n_used)
     return backward(theta, X, dY)
 
 

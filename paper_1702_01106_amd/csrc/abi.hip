@@ -591,6 +591,7 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
         stats->zone_stages = (int64_t)d.zone_stages;
         stats->n_resid_calls = (int64_t)d.resid_calls;
         stats->n_fallback = (int64_t)d.n_fallback;
+        stats->n_f64_retry = (int64_t)d.n_retry;
     }
     return GRIM_OK;
 }

@@ -28,7 +28,7 @@ struct Layout {
 // Device-side accumulators of the solver statistics.
 struct DevStats {
     unsigned long long iters[2];
-    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback;
+    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback, n_retry;
     unsigned long long max_resid_bits;
     unsigned int max_iters;
     unsigned int pad;
@@ -102,7 +102,11 @@ struct NewtonArgs {
     const float* mlp_y;    // if set: network output per zone [nz][kMlpOut] -> candidate guess
     double tol, eps, eps_bt;
     int k_max, ls_max;
+    // 0: one solve; 1: FP32 pass that marks failed zones kFlagRetry instead
+    // of counting them; 2: FP64 solve from P_n of the marked zones only
+    int pass;
 };
+constexpr uint8_t kFlagRetry = 32;
 
 // launchers (return hipSuccess or the launch error)
 hipError_t launch_fill_ghosts(const Layout& L, int nvar, const int bc[3], double* P, hipStream_t st);

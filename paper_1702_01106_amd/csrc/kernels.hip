@@ -444,14 +444,12 @@ __global__ __launch_bounds__(kBlock) void k_cfl(Layout L, Phys ph, GeoTables geo
 
 // ------------------------------------------------------------------ utilities
 
+// clears every field: the struct as 8-byte words, one lane per word
 __global__ void k_zero_stats(DevStats* s)
 {
-    if (threadIdx.x == 0) {
-        s->iters[0] = s->iters[1] = 0;
-        s->n_fail = s->n_ls = s->n_unphys = s->zone_stages = s->resid_calls = s->n_fallback = 0;
-        s->max_resid_bits = 0;
-        s->max_iters = 0;
-    }
+    static_assert(sizeof(DevStats) % 8 == 0 && sizeof(DevStats) / 8 <= 64, "DevStats layout");
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(s);
+    if (threadIdx.x < sizeof(DevStats) / 8) w[threadIdx.x] = 0ull;
 }
 
 __global__ __launch_bounds__(kBlock) void k_stream_add(const double* __restrict__ a, const double* __restrict__ b,

@@ -244,8 +244,9 @@ __global__ void k_out_grad(const float* __restrict__ O, const float* __restrict_
     float g = 0.0f;
     if (dY) {
         g = dY[t] * ys[j];
-    } else if (j < n_used) {
-        // loss in normalised output units: ((y - t) / y_scale)^2
+    } else if (j < n_used && ys[j] != 0.0f) {
+        // loss in normalised output units: ((y - t) / y_scale)^2; an output
+        // with y_scale 0 is held at zero and carries no loss
         const float d = (O[t] + b3[j]) - TB[t] / ys[j];
         g = 2.0f * d * inv_count;
         atomicAdd(loss, (double)d * (double)d * (double)inv_count);

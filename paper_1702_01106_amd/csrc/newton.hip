@@ -12,7 +12,10 @@
 //
 // JT selects the precision of the difference quotients, the stored Jacobian
 // and the LU: double (the plain method) or float (mixed precision; the
-// residual, conserved variables, metric and Lorentz factor stay FP64).
+// residual, conserved variables, metric and Lorentz factor stay FP64).  In
+// mixed precision a zone whose FP32 solve fails (in badly scaled zones the
+// FP32 Newton direction can be too inaccurate to converge) is marked, and a
+// second launch of the FP64 kernel solves only the marked zones from P_n.
 #include <hip/hip_runtime.h>
 
 #include "grim_internal.h"
@@ -121,7 +124,14 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
     const long z = (long)blockIdx.x * kWave + threadIdx.x;
     const Layout& L = a.s.L;
-    const bool active = z < L.nz;
+    const bool retry = a.pass == 2;
+    bool active = z < L.nz;
+    if (retry) {
+        active = active && (a.flags[z] & kFlagRetry);
+        if (__ballot(active) == 0ull) return;  // wave-uniform exit
+    }
+    const double* guess = retry ? nullptr : a.guess;
+    const float* mlp_y = retry ? nullptr : a.mlp_y;
     int iters = 0, ncalls = 0, fallback = 0;
     uint8_t fl = 0;
     double rr = 0.0;
@@ -147,10 +157,10 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
             // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
             nscale = a.s.dtp / (zc.g.gdet() * pn[RHO] * sn.ucon[0]);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) P[v] = a.guess ? a.guess[(long)v * L.nz + z] : pn[v];
-            if (a.mlp_y) {
+            for (int v = 0; v < NV; ++v) P[v] = guess ? guess[(long)v * L.nz + z] : pn[v];
+            if (mlp_y) {
                 // learned candidate: P = P_n + scaled network output
-                const float* y = a.mlp_y + z * kMlpOut;
+                const float* y = mlp_y + z * kMlpOut;
                 Pc_from_net<NV>(pn, y, P_alt);
             }
         }
@@ -162,7 +172,7 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
         ++ncalls;
         double r = nscale * sqrt(sumsq<NV>(R));
         bool from_net = false;
-        if (a.mlp_y) {
+        if (mlp_y) {
             // keep the learned guess only if its residual is smaller
 #pragma unroll
             for (int i = 0; i < 3; ++i) P_alt[B1 + i] = zc.rhs[B1 + i] * fB;
@@ -285,6 +295,7 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
         }
         rr = r;
         if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= 8;
+        if ((a.pass == 1 && (fl & (1 | 4 | 16))) || retry) fl |= kFlagRetry;
         if (a.s.floors) {
             const int ii = (int)(z % L.n[0]);
             const double r1 = exp(L.xs[0] + (ii + 0.5) * L.dx[0]);
@@ -299,23 +310,27 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = P[v];
         }
-        if (a.iters) a.iters[z] = iters;
+        if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + iters;
         if (a.resid) a.resid[z] = rr;
         if (a.flags) a.flags[z] = fl;
     }
 
-    // wave-level statistics, one atomic per wave
+    // wave-level statistics, one atomic per wave.  A zone marked for the
+    // FP64 retry contributes only its work (iterations, residual calls) to
+    // the FP32 pass; the retry pass reports its outcome.
     if (a.stats) {
+        const bool final_ = active && !(a.pass == 1 && (fl & kFlagRetry));
         const double sit = wave_sum(active ? (double)iters : 0.0);
         const int mit = wave_max(active ? iters : 0);
-        const double nf = wave_sum(active && (fl & (1 | 4 | 16)) ? 1.0 : 0.0);
-        const double nl = wave_sum(active && (fl & 2) ? 1.0 : 0.0);
-        const double nu = wave_sum(active && (fl & 8) ? 1.0 : 0.0);
-        const double na = wave_sum(active ? 1.0 : 0.0);
+        const double nf = wave_sum(final_ && (fl & (1 | 4 | 16)) ? 1.0 : 0.0);
+        const double nl = wave_sum(final_ && (fl & 2) ? 1.0 : 0.0);
+        const double nu = wave_sum(final_ && (fl & 8) ? 1.0 : 0.0);
+        const double na = wave_sum(active && !retry ? 1.0 : 0.0);
         const double nc = wave_sum(active ? (double)ncalls : 0.0);
         const double nfb = wave_sum(active ? (double)fallback : 0.0);
+        const double nrt = wave_sum(active && retry ? 1.0 : 0.0);
         unsigned long long rb = 0;
-        if (active) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
+        if (final_) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
         rb = wave_maxu64(rb);
         if (threadIdx.x == 0) {
             atomicAdd(&a.stats->iters[a.stage], (unsigned long long)sit);
@@ -323,7 +338,8 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
             if (nf > 0) atomicAdd(&a.stats->n_fail, (unsigned long long)nf);
             if (nl > 0) atomicAdd(&a.stats->n_ls, (unsigned long long)nl);
             if (nu > 0) atomicAdd(&a.stats->n_unphys, (unsigned long long)nu);
-            atomicAdd(&a.stats->zone_stages, (unsigned long long)na);
+            if (na > 0) atomicAdd(&a.stats->zone_stages, (unsigned long long)na);
+            if (nrt > 0) atomicAdd(&a.stats->n_retry, (unsigned long long)nrt);
             atomicAdd(&a.stats->resid_calls, (unsigned long long)nc);
             if (nfb > 0) atomicAdd(&a.stats->n_fallback, (unsigned long long)nfb);
             atomicMax(&a.stats->max_resid_bits, rb);
@@ -335,10 +351,21 @@ template <int NV, class G>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
-    if (jac_f32)
-        hipLaunchKernelGGL((k_newton<NV, G, float>), grid, blk, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, a);
+    if (jac_f32) {
+        // FP32 pass, then the FP64 retry of the zones it marks (needs flags)
+        if (!a.flags) return hipErrorInvalidValue;
+        NewtonArgs b = a;
+        b.pass = 1;
+        hipLaunchKernelGGL((k_newton<NV, G, float>), grid, blk, 0, st, b);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        b.pass = 2;
+        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
+    } else {
+        NewtonArgs b = a;
+        b.pass = 0;
+        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
+    }
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ GRIM_BC = {"periodic": 0, "outflow": 1, "polar": 2}
 GRIM_JAC = {"f64": 0, "f32": 1}
 GRIM_GUESS = {"pn": 0, "mlp": 1}
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 32, 128, 16, 22880
-FLAGS = {"NOT_CONVERGED": 1, "LS_EXHAUSTED": 2, "SINGULAR": 4, "UNPHYSICAL": 8, "NONFINITE": 16}
+FLAGS = {"NOT_CONVERGED": 1, "LS_EXHAUSTED": 2, "SINGULAR": 4, "UNPHYSICAL": 8, "NONFINITE": 16, "F64_RETRY": 32}
 
 
 class grim_config_t(C.Structure):
@@ -46,7 +46,7 @@ class grim_stats_t(C.Structure):
         ("mean_iters", C.c_double * 2), ("max_iters", C.c_int32), ("pad", C.c_int32),
         ("n_fail", C.c_int64), ("n_ls_exhausted", C.c_int64), ("n_unphysical", C.c_int64),
         ("max_resid", C.c_double), ("zone_stages", C.c_int64), ("n_resid_calls", C.c_int64),
-        ("n_fallback", C.c_int64),
+        ("n_fallback", C.c_int64), ("n_f64_retry", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -60,6 +60,7 @@ class grim_stats_t(C.Structure):
             "zone_stages": int(self.zone_stages),
             "n_resid_calls": int(self.n_resid_calls),
             "n_fallback": int(self.n_fallback),
+            "n_f64_retry": int(self.n_f64_retry),
         }
 
 

@@ -36,14 +36,16 @@ def collect(wl: dict, seeds, steps: int, stride: int, cap: int):
 
 
 def normalisation(X, T, n_used: int):
-    """Input mean and 1/std (0 for constant inputs), output std (1 if unused)."""
+    """Input mean and 1/std (0 for constant inputs); output std, 0 for an
+    output that is constant over the pairs (for example the third velocity
+    of a 2-D run) or unused, which holds that output at exactly zero."""
     x = X.double()
     xm = x.mean(dim=0)
     xs = x.std(dim=0)
     istd = np.where(xs.cpu().numpy() > 0, 1.0 / np.maximum(xs.cpu().numpy(), 1e-300), 0.0)
-    ys = np.ones(grim.MLP_OUT)
+    ys = np.zeros(grim.MLP_OUT)
     t = T.double()[:, :n_used].std(dim=0).cpu().numpy()
-    ys[:n_used] = np.where(t > 0, t, 1.0)
+    ys[:n_used] = np.where(t > 0, t, 0.0)
     return xm.cpu().numpy(), istd, ys
 
 

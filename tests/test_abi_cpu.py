@@ -82,3 +82,13 @@ def test_oracle_not_imported_by_product():
     for f in ("grim.py", "workloads.py", "build.py", "__init__.py"):
         src = open(os.path.join(ROOT, "paper_1702_01106_amd", f)).read()
         assert "oracle" not in src.replace("oracle's", "")
+
+
+def test_flag_constants_match_header():
+    import re
+
+    from paper_1702_01106_amd import grim
+
+    hdr = open(os.path.join(ROOT, "include", "grim.h")).read()
+    found = dict(re.findall(r"#define GRIM_FLAG_(\w+) (\d+)", hdr))
+    assert {k: int(v) for k, v in found.items()} == grim.FLAGS

@@ -3,7 +3,16 @@
 Every GPU result here is compared element by element with the oracle on the
 same seeded inputs.  Tolerances: the plain FP64 path must satisfy the
 oracle's own residual (< 2 tol) and agree per primitive to 1e-6 of
-max(|P_v|, RMS of its family); in practice the two agree to ~1e-12.
+max(|P_v|, RMS of its family); in Minkowski the two agree to ~1e-12.
+
+Kerr: the two sides build the metric derivatives with different difference
+stencils, so their geometry differs at ~1e-9 relative.  Newton stops
+anywhere below the tolerance, and in the thin atmosphere a 1e-9 change of
+the input moves the root by up to ~1e-6 of the (near-zero) scale of q and
+DP.  There the forward error is bounded by the oracle's own spread: the
+largest change of the oracle's answer when its input is perturbed by 1e-9
+relative (`_oracle_spread`), with a margin of 10.  The oracle's residual at
+the GPU root stays the strict check.
 """
 import sys
 
@@ -55,6 +64,25 @@ def _floored(wl, P):
     return fl.ravel()
 
 
+def _oracle_spread(run, P, rel=1e-9, seed=11, base=None):
+    """Per-primitive max change of run(P) (the oracle) under a relative
+    perturbation `rel` of P, and the fraction of zones whose iteration count
+    stays the same.  `run` returns (prims, iters); `base` is run(P) if known."""
+    rng = np.random.default_rng(seed)
+    a, ia = run(P) if base is None else base
+    b, ib = run(P * (1.0 + rel * rng.uniform(-1, 1, P.shape)))
+    e = prim_rel_err(b, a).reshape(P.shape[0], -1).max(axis=1)
+    same = 1.0 if ia is None else float(np.mean(ia == ib))
+    return e, same
+
+
+def _within_spread(err, spread, floor):
+    """err (nvar x zones) against max(floor, 10 x the oracle's spread) per primitive."""
+    e = err.reshape(spread.shape[0], -1).max(axis=1)
+    bound = np.maximum(floor, 10.0 * spread)
+    assert np.all(e <= bound), (e, bound)
+
+
 CASES = {
     # name: (workload dict, initial state)
     "srmhd1d": lambda: (W.workload("srmhd1d_alfven_128"), None),
@@ -97,10 +125,13 @@ def test_explicit_stage(torch_cuda, oracle_mod, name):
     g = _ctx(wl)
     gdF, gsrc, gsp = g.explicit(P)
     gdF, gsrc, gsp = gdF.cpu().numpy(), gsrc.cpu().numpy(), gsp.cpu().numpy()
-    # Kerr: the two sides build g^{mu nu} (closed form vs numeric inverse) and
-    # Gamma (4th- vs 2nd-order differences) independently: ~1e-10 relative
+    # Kerr: the two sides build g^{mu nu} independently (closed form against
+    # a numeric inverse) and difference the metric with their own code
     kerr = name in KERR
     tdf, tsrc = (1e-9, 1e-7) if kerr else (1e-11, 1e-12)
+    _say("  max rel err divF %.1e src %.1e" % (
+        max(np.abs(gdF[v] - dF[v]).max() / max(np.abs(dF[v]).max(), 1e-300) for v in range(wl["nvar"])),
+        np.abs(gsrc - src).max() / max(np.abs(src).max(), 1.0)))
     for v in range(wl["nvar"]):
         scale = max(np.abs(dF[v]).max(), 1e-300)
         assert np.abs(gdF[v] - dF[v]).max() <= tdf * scale + 1e-13, (v, np.abs(gdF[v] - dF[v]).max(), scale)
@@ -148,17 +179,30 @@ def test_stage_solve(torch_cuda, oracle_mod, name, jac):
     gP, git, grr, gfl = g.stage_solve(Pn, PE, dtp)
     gP = gP.cpu().numpy()
     git, grr, gfl = git.cpu().numpy(), grr.cpu().numpy(), gfl.cpu().numpy()
-    assert np.all(gfl == 0), np.unique(gfl)
+    # FP32 Jacobian: a zone whose FP32 solve fails is solved again with the
+    # FP64 Jacobian (flag 32); no zone may fail in the end
+    retried = int(np.sum(gfl & 32))
+    if retried:
+        _say(f"  zones solved again with the FP64 Jacobian: {retried // 32}")
+    assert jac == "f32" or retried == 0
+    assert np.all((gfl & ~np.uint8(32)) == 0), np.unique(gfl)
     err = prim_rel_err(gP, ref)
-    assert err.max() < 1e-6, err.max()
     # the oracle's own residual at the GPU root (zones whose output was
     # floored after the solve are not roots by construction)
     _, rn = o.residual(Pn, PE, dtp, gP)
     live = ~_floored(wl, gP)
     assert rn[live].max() < 2 * wl["tol"], rn[live].max()
     assert grr.max() < wl["tol"]
+    if name in KERR:
+        spread, same = _oracle_spread(lambda Q: o.stage(Q, PE, dtp)[:2], Pn, base=(ref, it))
+        _say(f"  oracle spread {np.array2string(spread, precision=1)} same-iters {same:.3f}")
+        _within_spread(err, spread, 1e-8 if jac == "f64" else 1e-6)
+        if jac == "f64":
+            assert np.mean(git == it) >= same - 0.05, (np.mean(git == it), same)
+        return
+    assert err.max() < 1e-6, err.max()
     if jac == "f64":
-        assert err.max() < (1e-7 if name in KERR else 1e-8), err.max()
+        assert err.max() < 1e-8, err.max()
         assert np.mean(git == it) > 0.98
 
 
@@ -179,6 +223,11 @@ def test_steps(torch_cuda, oracle_mod, name):
     assert gst["n_fail"] == st["n_fail"]
     # zones that stop one iteration apart differ by up to the Newton tolerance
     err = prim_rel_err(gP, ref)
+    if name in KERR:
+        spread, _ = _oracle_spread(lambda Q: (o.step(Q, dt, nsteps)[0], None), P0, base=(ref, None))
+        _say(f"  oracle spread {np.array2string(spread, precision=1)}")
+        _within_spread(err, spread, 1e-6)
+        return
     assert err.max() < 1e-6, err.max()
     for s in range(2):
         assert abs(gst["mean_iters"][s] - st["mean_iters"][s]) <= 0.01 * st["mean_iters"][s] + 1e-9
@@ -240,6 +289,25 @@ def test_failure_flags_match_oracle(torch_cuda, oracle_mod):
     assert np.array_equal(gfl.ravel() & 16, ofl & 16)
 
 
+def test_f64_retry_of_failed_f32_zones(torch_cuda):
+    """Forced from the host: with k_max = 1 and tol = 1e-14 every FP32 solve
+    fails, so every zone is solved again from P_n with the FP64 Jacobian; the
+    result must then equal the plain FP64 solve bit for bit, with the same
+    flags plus GRIM_FLAG_F64_RETRY, and the iteration counts of both passes."""
+    wl = dict(W.small("emhd2d_modes_256", [24, 20]), k_max=1, tol=1e-14)
+    Pn = W.fourier_modes_2d(wl, seed=7, amp=5e-2)
+    dtp = 2e-3
+    a = _ctx(dict(wl, jac="f64"))
+    b = _ctx(dict(wl, jac="f32"))
+    P64, it64, r64, fl64 = (x.cpu().numpy() for x in a.stage_solve(Pn, Pn, dtp))
+    P32, it32, r32, fl32 = (x.cpu().numpy() for x in b.stage_solve(Pn, Pn, dtp))
+    assert np.all(fl64 & 1)
+    assert np.array_equal(fl32, fl64 | 32)
+    assert np.array_equal(P32, P64)
+    assert np.array_equal(r32, r64)
+    assert np.array_equal(it32, it64 + 1)
+
+
 def test_cfl_and_stream(torch_cuda, oracle_mod):
     wl = W.small("emhd2d_modes_256", [64, 64])
     P = W.fourier_modes_2d(wl, seed=1)
@@ -298,16 +366,18 @@ def test_kerr_full_size(torch_cuda, oracle_mod, name):
     g.set_prims(P0)
     dt = g.cfl_dt(wl["cfl"])
     assert abs(dt - o.cfl_dt(P0, wl["cfl"])) <= 1e-12 * dt
-    _say(f"{name}: oracle stage on the full grid")
+    _say(f"{name}: oracle stage on the full grid (twice, for its spread)")
     ref, it, rr, fl = o.stage(P0, P0, 0.5 * dt)
+    assert np.all(fl == 0), np.unique(fl, return_counts=True)
+    spread, _ = _oracle_spread(lambda Q: o.stage(Q, P0, 0.5 * dt)[:2], P0, base=(ref, it))
+    _say(f"  oracle spread {np.array2string(spread, precision=1)}")
     for jac in ("f64", "f32"):
         gj = _ctx(dict(wl, jac=jac))
         gP, git, grr, gfl = gj.stage_solve(P0, P0, 0.5 * dt)
-        gfl = gfl.cpu().numpy()
-        ok = (gfl == 0) & (fl == 0)
-        assert np.mean(ok) > 0.999
-        err = prim_rel_err(gP.cpu().numpy(), ref).reshape(wl["nvar"], -1)[:, ok]
-        assert err.max() < 1e-6, (jac, err.max())
+        gP, gfl = gP.cpu().numpy(), gfl.cpu().numpy()
+        assert np.all(gfl == 0), (jac, np.unique(gfl, return_counts=True))
+        assert grr.max().item() < wl["tol"]
+        _within_spread(prim_rel_err(gP, ref), spread, 1e-8 if jac == "f64" else 1e-6)
         gj.close()
     _say(f"{name}: {wl['steps']} GPU steps")
     st = g.run(dt, wl["steps"], use_graph=True)

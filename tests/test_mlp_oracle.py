@@ -73,3 +73,28 @@ def test_bf16_rounding():
     assert M.bf16(np.array(1.0 + one_ulp / 2))[()] == 1.0               # tie -> even (1.0)
     assert M.bf16(np.array(1.0 + 1.5 * one_ulp))[()] == 1.0 + 2 * one_ulp  # tie -> even
     assert M.bf16(np.array(1.0 + 0.6 * one_ulp))[()] == 1.0 + one_ulp
+
+
+def test_zero_scale_output_is_held_at_zero():
+    """An output with y_scale 0 is exactly zero, carries no loss and gets no
+    gradient; the other outputs are unaffected."""
+    rng = np.random.default_rng(7)
+    ys = rng.uniform(0.5, 2, M.D_OUT)
+    th = M.init_params(4, y_scale=ys)
+    ys0 = ys.copy()
+    ys0[2] = 0.0
+    th0 = M.init_params(4, y_scale=ys0)
+    X = rng.normal(size=(5, M.D_IN))
+    T = rng.normal(size=(5, M.D_OUT))
+    T0 = T.copy()
+    T0[:, 2] = 0.0
+    y, y0 = M.forward(th, X), M.forward(th0, X)
+    assert np.all(y0[:, 2] == 0.0)
+    assert np.array_equal(np.delete(y0, 2, axis=1), np.delete(y, 2, axis=1))
+    # loss without output 2: the same sum, the same 7-output denominator
+    d = ((y - T) / ys)[:, :7]
+    d[:, 2] = 0.0
+    assert abs(M.mse_loss(th0, X, T0, 7) - np.mean(d * d)) < 1e-15
+    g = M.mse_grad(th0, X, T0, 7)
+    W3 = M.unpack(g)["W3"]
+    assert np.all(W3[:, 2] == 0.0) and np.any(W3[:, 1] != 0.0)

@@ -504,7 +504,7 @@ def test_mks_connection_contracted_identity(oracle_mod):
         d1 = 2 * r * r / Sig + 1.0
         d2 = dth * (-2 * a * a * np.cos(th) * np.sin(th) / Sig + np.cos(th) / np.sin(th)) + ddth / dth
         ref = np.array([0.0, d1, d2, 0.0])
-        assert np.allclose(contracted, ref, rtol=1e-7, atol=1e-8), (contracted, ref)
+        assert np.allclose(contracted, ref, rtol=1e-8, atol=1e-10), (contracted, ref)
 
 
 def test_mks_metric_compatibility(oracle_mod):
