@@ -1,10 +1,8 @@
 // The learned initial guess: a 32 -> 128 -> 128 -> 16 GELU network.
 //
 // Inference (a14) is BF16 on the matrix cores with FP32 accumulation
-// (v_mfma_f32_32x32x8_bf16): a block of four waves takes 128 rows, each wave
-// 32 rows; the transposed BF16 weights sit in LDS, and each hidden layer goes
-// through LDS once to turn the MFMA result layout into the next layer's
-// A-operand layout.  Training (a15) is FP32 on the vector units: a tiled
+// (v_mfma_f32_32x32x8_bf16), one wave per 32 rows, evaluated transposed so the
+// activations never leave registers; the transposed BF16 weights sit in LDS.  Training (a15) is FP32 on the vector units: a tiled
 // GEMM, elementwise GELU / loss kernels and Adam on FP32 master weights.
 //
 // Parameter vector (FP32): W1 [32][128], b1, W2 [128][128], b2, W3 [128][16],
@@ -63,29 +61,73 @@ __global__ void k_mlp_pack(const float* __restrict__ p, unsigned short* __restri
 
 // ------------------------------------------------------------------ inference
 
+// The network is evaluated transposed, Z^T = W^T X^T, so that each wave's 32
+// rows are the N dimension of v_mfma_f32_32x32x8_bf16.  Operand layouts of that
+// instruction (lane l, e = 0..3): A[m = l%32][k = 4(l/32) + e],
+// B[k = 4(l/32) + e][n = l%32]; accumulator element r of lane l is
+// D[m = 8(r/4) + 4(l/32) + r%4][n = l%32].  A hidden layer's accumulator
+// elements 4q..4q+3 of output tile t are therefore exactly the B operand of
+// k-step 4t + q of the next layer: activations stay in registers, and only
+// the transposed BF16 weights (the A operands) live in LDS.
 constexpr int kRowsPerWave = 32;
 constexpr int kWaves = 4;
-constexpr int kRowsPerBlock = kRowsPerWave * kWaves;
-constexpr int kHStride = DH + 8;  // bf16 elements per LDS row (padding spreads banks)
+// LDS row strides in bf16 elements: K + 4 puts the 8-byte reads of the 32
+// lanes of a half-wave on distinct banks
+constexpr int kS1 = DI + 4, kS2 = DH + 4;
 
-// Accumulator element r of lane l sits at row 8 (r/4) + 4 (l/32) + r%4, column l%32.
-__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
-
-__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ X, long n, const float* __restrict__ p,
-                                                   const unsigned short* __restrict__ w1t,
-                                                   const unsigned short* __restrict__ w2t,
-                                                   const unsigned short* __restrict__ w3t, float* __restrict__ Y)
+// gelu(z) = z (1 + erf(z / sqrt 2)) / 2 with erf from Abramowitz & Stegun
+// 7.1.26 (absolute error below 1.5e-7, far under the BF16 rounding that
+// follows); the training path keeps erff.
+__device__ __forceinline__ float gelu_fast(float z)
 {
-    __shared__ unsigned short sW1[DH * DI];
-    __shared__ unsigned short sW2[DH * DH];
-    __shared__ unsigned short sW3[32 * DH];
-    __shared__ unsigned short sH[kWaves][kRowsPerWave * kHStride];
+    const float ax = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float p = fmaf(t, 1.061405429f, -1.453152027f);
+    p = fmaf(t, p, 1.421413741f);
+    p = fmaf(t, p, -0.284496736f);
+    p = fmaf(t, p, 0.254829592f);
+    p *= t;
+    const float e = 1.0f - p * __expf(-ax * ax);
+    return 0.5f * z * (1.0f + copysignf(e, z));
+}
+
+__device__ __forceinline__ bf16x4 lds_a(const unsigned short* base)
+{
+    // 8-byte aligned: every row stride and k offset is a multiple of 4 elements
+    return *reinterpret_cast<const bf16x4*>(base);
+}
+
+__global__ __launch_bounds__(kWaves * 64, 3) void k_mlp_infer(const float* __restrict__ X, long n,
+                                                           const float* __restrict__ p,
+                                                           const unsigned short* __restrict__ w1t,
+                                                           const unsigned short* __restrict__ w2t,
+                                                           const unsigned short* __restrict__ w3t,
+                                                           float* __restrict__ Y)
+{
+    __shared__ __align__(16) unsigned short sW1[DH * kS1];
+    __shared__ __align__(16) unsigned short sW2[DH * kS2];
+    __shared__ __align__(16) unsigned short sW3[32 * kS2];
     __shared__ float sB1[DH], sB2[DH], sB3[32], sXm[DI], sXs[DI], sYs[32];
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < DH * DI; i += 256) sW1[i] = w1t[i];
-    for (int i = tid; i < DH * DH; i += 256) sW2[i] = w2t[i];
-    for (int i = tid; i < 32 * DH; i += 256) sW3[i] = w3t[i];
+    // stage the transposed weights, 4 bf16 (8 bytes) per access
+    {
+        const uint2* g1 = reinterpret_cast<const uint2*>(w1t);
+        for (int i = tid; i < DH * DI / 4; i += kWaves * 64) {
+            const int r = i / (DI / 4), c = 4 * (i % (DI / 4));
+            *reinterpret_cast<uint2*>(&sW1[r * kS1 + c]) = g1[i];
+        }
+        const uint2* g2 = reinterpret_cast<const uint2*>(w2t);
+        for (int i = tid; i < DH * DH / 4; i += kWaves * 64) {
+            const int r = i / (DH / 4), c = 4 * (i % (DH / 4));
+            *reinterpret_cast<uint2*>(&sW2[r * kS2 + c]) = g2[i];
+        }
+        const uint2* g3 = reinterpret_cast<const uint2*>(w3t);
+        for (int i = tid; i < 32 * DH / 4; i += kWaves * 64) {
+            const int r = i / (DH / 4), c = 4 * (i % (DH / 4));
+            *reinterpret_cast<uint2*>(&sW3[r * kS2 + c]) = g3[i];
+        }
+    }
     if (tid < DH) {
         sB1[tid] = p[kOffB1 + tid];
         sB2[tid] = p[kOffB2 + tid];
@@ -98,84 +140,80 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ X, 
     }
     __syncthreads();
 
-    const int wave = tid >> 6, lane = tid & 63;
-    const int col = lane & 31, half = lane >> 5;
-    unsigned short* H = sH[wave];
-    const long ntiles = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long row0 = tile * kRowsPerBlock + (long)wave * kRowsPerWave;
-        // ---- layer 1: A = normalised input rows (K = 32, four k-steps of 8)
-        bf16x4 a1[4];
-        {
-            const long row = row0 + col;
+    // one 32-row tile per wave (no tile loop: the weight reads below would be
+    // hoisted out of it as loop invariants and spilled)
+    const int lane = tid & 63;
+    const int c = lane & 31, h = lane >> 5;
+    const long tile = (long)blockIdx.x * kWaves + (tid >> 6);
+    {
+        const long row = tile * kRowsPerWave + c;
+        const bool live = row < n;
+
+        // ---- layer 1, B = normalised X^T: k = 8s + 4h + e of row `row`
+        bf16x4 bx[DI / 8];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = 8 * s + 4 * half + e;
-                    const float x = row < n ? (X[row * DI + k] - sXm[k]) * sXs[k] : 0.0f;
-                    a1[s][e] = (short)to_bf16(x);
-                }
+        for (int s = 0; s < DI / 8; ++s) {
+            const int k0 = 8 * s + 4 * h;
+            float4 x = live ? *reinterpret_cast<const float4*>(X + row * DI + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            bx[s][0] = (short)to_bf16((x.x - sXm[k0 + 0]) * sXs[k0 + 0]);
+            bx[s][1] = (short)to_bf16((x.y - sXm[k0 + 1]) * sXs[k0 + 1]);
+            bx[s][2] = (short)to_bf16((x.z - sXm[k0 + 2]) * sXs[k0 + 2]);
+            bx[s][3] = (short)to_bf16((x.w - sXm[k0 + 3]) * sXs[k0 + 3]);
         }
+        bf16x4 b2[DH / 8];
 #pragma unroll
         for (int t = 0; t < DH / 32; ++t) {
             f32x16 acc = {};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                bf16x4 b;
+            for (int s = 0; s < DI / 8; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds_a(&sW1[(32 * t + c) * kS1 + 8 * s + 4 * h]), bx[s],
+                                                              acc, 0, 0, 0);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = (short)sW1[(32 * t + col) * DI + 8 * s + 4 * half + e];
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[s], b, acc, 0, 0, 0);
-            }
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                H[acc_row(r, lane) * kHStride + 32 * t + col] = to_bf16(gelu(acc[r] + sB1[32 * t + col]));
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 32 * t + 8 * q + 4 * h + e;
+                    b2[4 * t + q][e] = (short)to_bf16(gelu_fast(acc[4 * q + e] + sB1[m]));
+                }
         }
-        __syncthreads();  // hidden activations visible in LDS
-        // ---- layer 2: K = 128 (sixteen k-steps)
+        // ---- layer 2: k-steps outer, the four output tiles inner
         f32x16 acc2[DH / 32];
 #pragma unroll
         for (int t = 0; t < DH / 32; ++t) acc2[t] = f32x16{};
 #pragma unroll
-        for (int s = 0; s < DH / 8; ++s) {
-            bf16x4 a;
+        for (int s = 0; s < DH / 8; ++s)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = (short)H[col * kHStride + 8 * s + 4 * half + e];
-#pragma unroll
-            for (int t = 0; t < DH / 32; ++t) {
-                bf16x4 b;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = (short)sW2[(32 * t + col) * DH + 8 * s + 4 * half + e];
-                acc2[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc2[t], 0, 0, 0);
-            }
-        }
-        __syncthreads();
+            for (int t = 0; t < DH / 32; ++t)
+                acc2[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds_a(&sW2[(32 * t + c) * kS2 + 8 * s + 4 * h]),
+                                                                  b2[s], acc2[t], 0, 0, 0);
+        bf16x4 b3[DH / 8];
 #pragma unroll
         for (int t = 0; t < DH / 32; ++t)
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                H[acc_row(r, lane) * kHStride + 32 * t + col] = to_bf16(gelu(acc2[t][r] + sB2[32 * t + col]));
-        __syncthreads();
-        // ---- layer 3: one 32 x 32 output tile (columns >= 16 are zero padding)
-        f32x16 acc3 = {};
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int s = 0; s < DH / 8; ++s) {
-            bf16x4 a, b;
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 32 * t + 8 * q + 4 * h + e;
+                    b3[4 * t + q][e] = (short)to_bf16(gelu_fast(acc2[t][4 * q + e] + sB2[m]));
+                }
+        // ---- layer 3: 32 output rows of which the first 16 are real
+        f32x16 acc = {};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                a[e] = (short)H[col * kHStride + 8 * s + 4 * half + e];
-                b[e] = (short)sW3[col * DH + 8 * s + 4 * half + e];
+        for (int s = 0; s < DH / 8; ++s)
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds_a(&sW3[c * kS2 + 8 * s + 4 * h]), b3[s], acc, 0, 0, 0);
+        if (live) {
+            // elements 0..3: outputs 4h..4h+3; 4..7: outputs 8+4h..8+4h+3
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const int m0 = 8 * g + 4 * h;
+                float4 y;
+                y.x = (acc[4 * g + 0] + sB3[m0 + 0]) * sYs[m0 + 0];
+                y.y = (acc[4 * g + 1] + sB3[m0 + 1]) * sYs[m0 + 1];
+                y.z = (acc[4 * g + 2] + sB3[m0 + 2]) * sYs[m0 + 2];
+                y.w = (acc[4 * g + 3] + sB3[m0 + 3]) * sYs[m0 + 3];
+                *reinterpret_cast<float4*>(Y + row * DO + m0) = y;
             }
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc3, 0, 0, 0);
         }
-        if (col < DO) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const long row = row0 + acc_row(r, lane);
-                if (row < n) Y[row * DO + col] = (acc3[r] + sB3[col]) * sYs[col];
-            }
-        }
-        __syncthreads();  // the next tile reuses H
     }
 }
 
@@ -304,9 +342,13 @@ hipError_t mlp_infer(const float* X, long n, const float* params, const unsigned
                      const unsigned short* w2t, const unsigned short* w3t, float* Y, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const long tiles = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    const unsigned grid = (unsigned)std::min<long>(tiles, 1024);
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, st, X, n, params, w1t, w2t, w3t, Y);
+    // X rows and Y rows are read / written as 16-byte vectors
+    if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) return hipErrorInvalidValue;
+    const long tiles = (n + kRowsPerWave - 1) / kRowsPerWave;
+    const long blocks = (tiles + kWaves - 1) / kWaves;
+    if (blocks > 0x7FFFFFFFL) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)blocks;
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(kWaves * 64), 0, st, X, n, params, w1t, w2t, w3t, Y);
     return hipGetLastError();
 }
 
