@@ -31,19 +31,22 @@ HBM_PEAK_GBS = 8000.0
 # FP64 operations (fma = 2, sqrt = div = 1) of one residual evaluation R(P)
 # in Minkowski coordinates, counted on the specialised register code: derive
 # the state, T^0_nu, U(P), and for EMHD the rescaled q, DP and the implicit
-# relaxation terms.  Norm: 2N + 2.  Jacobian column: perturbation (4), the
-# reciprocal of h (1), N subtractions and N multiplications.  LU with partial
-# pivoting and one right-hand side: 2N^3/3 + 2N^2 (rounded, below).
+# relaxation terms.  The Newton system has N = nvar - 3 unknowns (5 ideal,
+# 7 EMHD: B is fixed at its explicit update).  Norm over the system rows:
+# 2N + 2.  Jacobian column: perturbation (4), the reciprocal of h (1), N
+# subtractions and N multiplications.  Dense solve with partial pivoting and
+# one right-hand side, counted as LU: 2N^3/3 + 2N^2 (rounded, below).
 RESID_FLOPS = {8: 66, 10: 157}
-LU_FLOPS = {8: 469, 10: 867}
+LU_FLOPS = {5: 133, 7: 327}
 
 
 def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) -> float:
-    """Algorithmic FP64 flops of the Newton solves summed over a run."""
-    n = nvar
+    """Algorithmic FP64 flops of the Newton solves summed over a run (the
+    learned-guess candidate check counts as one more residual call)."""
+    n = nvar - 3
     ls_trials = resid_calls - zone_stages - n * iters
     norm = 2 * n + 2
-    return (resid_calls * RESID_FLOPS[n]
+    return (resid_calls * RESID_FLOPS[nvar]
             + (zone_stages + ls_trials) * norm
             + iters * (n * (2 * n + 5) + LU_FLOPS[n])
             + ls_trials * 2 * n)
@@ -252,7 +255,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "zones": zones, "nvar": nvar, "steps_in_workload": wl["steps"],
-                   "tol": wl["tol"], "jacobian": "f64", "dt": dt},
+                   "tol": wl["tol"], "jacobian": "f64", "guess": "P_n", "dt": dt},
         "mean_newton_iters": st["mean_iters"],
         "max_resid": st["max_resid"],
         "n_fail": st["n_fail"],

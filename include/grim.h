@@ -166,9 +166,10 @@ int grim_cfl_dt(grim_ctx_t* ctx, double cfl, double* dt);
 int grim_run(grim_ctx_t* ctx, double dt, int nsteps, int use_graph, grim_stats_t* stats);
 
 /* Test hook for a8: the residual R(P) of every interior zone for a stage with
- * P_n, P^E and dt' (eqs. half_step_residual / full_step), and the scaled norm
- * ||R|| = sqrt(sum_v (dt' R_v)^2) / U_rho(P_n).  All pointers device, interior
- * layout; rnorm may be NULL. */
+ * P_n, P^E and dt' (eqs. half_step_residual / full_step), all nvar rows, and
+ * the scaled Newton norm ||R|| = sqrt(sum_v (dt' R_v)^2) / U_rho(P_n) over
+ * the rows of the Newton system (the non-magnetic rows, Sec. 8.2).  All
+ * pointers device, interior layout; rnorm may be NULL. */
 int grim_residual(grim_ctx_t* ctx, const double* Pn, const double* PE, double dtp,
                   const double* P, double* R, double* rnorm);
 
@@ -196,8 +197,11 @@ int grim_get_zone_results(grim_ctx_t* ctx, uint8_t* flags, int32_t* iters, int o
  * enqueues steps eagerly (no graph) and brackets every launch group with HIP
  * events on the context's stream.  grim_kernel_times synchronises and returns,
  * per kernel group, the summed device time in ms and the number of launches,
- * then clears the records.  Groups: 0 ghost fill, 1 face fluxes, 2 flux-CT
- * EMFs, 3 stage right-hand side, 4 Newton solve (n = 5 entries). */
+ * then clears the records.  Groups: 0 ghost fill (no longer launched inside
+ * a step: the Newton kernel writes the ghosts), 1 face fluxes (all
+ * directions, one launch), 2 flux-CT EMFs (now evaluated inside the stage
+ * right-hand side: always empty), 3 stage right-hand side, 4 Newton solve,
+ * 5 network inference (n = 6 entries). */
 int grim_profile(grim_ctx_t* ctx, int enable);
 int grim_kernel_times(grim_ctx_t* ctx, double* ms, int64_t* launches, int n);
 

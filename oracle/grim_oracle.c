@@ -857,6 +857,28 @@ static void o_zone_residual(void* ctx, const double* P, double* R)
     }
 }
 
+/* The Newton unknowns are the non-magnetic primitives (Sec. 8.2: a 5x5
+ * Jacobian over {rho, u, u^1, u^2, u^3} for ideal MHD, 7x7 with q and DP for
+ * EMHD).  B is held at its explicit update, the root of the induction rows,
+ * which depend on B alone; the system is the residual's non-magnetic rows. */
+static const int o_unknown[7] = {RHO, UU, U1, U2, U3, QQ, DP};
+
+typedef struct {
+    ozone_t* z;
+    double P[NVMAX]; /* full primitive vector; B entries fixed */
+    int m;           /* number of unknowns: nvar - 3 */
+} oreduced_t;
+
+static void o_reduced_residual(void* ctx, const double* x, double* R)
+{
+    oreduced_t* q = (oreduced_t*)ctx;
+    double P[NVMAX], Rf[NVMAX];
+    for (int v = 0; v < NVMAX; ++v) P[v] = q->P[v];
+    for (int i = 0; i < q->m; ++i) P[o_unknown[i]] = x[i];
+    o_zone_residual(q->z, P, Rf);
+    for (int i = 0; i < q->m; ++i) R[i] = Rf[o_unknown[i]];
+}
+
 static void o_zone_setup(const ocfg_t* c, const double X[4], const double* Pn, const double* PE,
                          const double* divF_z, const double* srcE_z, const oemhd_sp_t* sp, double dtp,
                          ozone_t* z)
@@ -929,8 +951,15 @@ int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp
                 int32_t it = 0;
                 double rr = 0.0;
                 uint8_t fl = 0;
-                oracle_newton_generic(nv, o_zone_residual, &Z, P, dtp / urho_n, c->tol, c->eps, c->eps_bt,
+                oreduced_t Q;
+                Q.z = &Z;
+                Q.m = nv - 3;
+                for (int v = 0; v < NVMAX; ++v) Q.P[v] = v < nv ? P[v] : 0.0;
+                double x[7];
+                for (int i = 0; i < Q.m; ++i) x[i] = P[o_unknown[i]];
+                oracle_newton_generic(Q.m, o_reduced_residual, &Q, x, dtp / urho_n, c->tol, c->eps, c->eps_bt,
                                       c->k_max, c->ls_max, &it, &rr, &fl);
+                for (int i = 0; i < Q.m; ++i) P[o_unknown[i]] = x[i];
                 if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= OFLAG_UNPHYSICAL;
                 if (c->floors) {
                     double r = exp(X[1]);
@@ -1035,7 +1064,12 @@ int oracle_residual(const ocfg_t* c, const double* Pn, const double* PE, double 
                 o_zone_setup(c, X, pn, pe, dz, sz, &sp[z], dtp, &Z);
                 o_zone_residual(&Z, p, r);
                 for (int v = 0; v < nv; ++v) R[(size_t)v * nz + z] = r[v];
-                if (rnorm) rnorm[z] = o_norm(nv, r, dtp / Z.Un[RHO]);
+                if (rnorm) {
+                    /* the Newton norm: over the system rows (B rows excluded) */
+                    double rs[7];
+                    for (int i = 0; i < nv - 3; ++i) rs[i] = r[o_unknown[i]];
+                    rnorm[z] = o_norm(nv - 3, rs, dtp / Z.Un[RHO]);
+                }
             }
     free(PEg);
     free(divF);

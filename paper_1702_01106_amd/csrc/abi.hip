@@ -193,6 +193,7 @@ NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
     a.resid = c->resid;
     a.flags = c->flags;
     a.stats = c->stats;
+    for (int d = 0; d < 3; ++d) a.bc[d] = c->cfg.bc[d];
     return a;
 }
 
@@ -239,10 +240,6 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
             Timed t(c, 1, st);
             HIP_TRY(c, grim::launch_fluxes(s, c->nvar, c->cfg.metric, st));
         }
-        if (c->cfg.ndim >= 2) {
-            Timed t(c, 2, st);
-            HIP_TRY(c, grim::launch_emf(s, st));
-        }
         {
             Timed t(c, 3, st);
             HIP_TRY(c, grim::launch_rhs(s, c->nvar, c->cfg.metric, st));
@@ -257,6 +254,7 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     NewtonArgs n = newton_args(c, s);
     n.out = out;
     n.out_ghosted = 1;
+    n.write_ghosts = 1;  // the output's ghosts are written with it
     n.stage = stage;
     n.mlp_y = net ? c->mlp_y : nullptr;
     {
@@ -274,23 +272,16 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
 }
 
 // One full step from buffer `from` into the other buffer, enqueued on st.
+// The state buffers always hold valid ghosts: grim_set_prims fills them, and
+// each stage's Newton kernel writes the ghost images of every zone it solves.
 int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st, Collect* col = nullptr)
 {
     double* A = c->P[from];
     double* B = c->P[1 - from];
-    const int bc[3] = {c->cfg.bc[0], c->cfg.bc[1], c->cfg.bc[2]};
-    {
-        Timed t(c, 0, st);
-        HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, A, st));
-    }
     int rc = enqueue_stage(c, A, A, 0.5 * dt, B, 0, st, col);
     if (rc) return rc;
-    {
-        Timed t(c, 0, st);
-        HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, B, st));
-    }
-    // stage 2 writes P_{n+1} over P^E = P_{n+1/2}: each lane reads its own
-    // zone of P^E before writing it, and nothing else reads P^E then.
+    // stage 2 writes P_{n+1} (and its ghosts) over P^E = P_{n+1/2}: the
+    // Newton kernel does not read P^E, which the flux stage has consumed.
     return enqueue_stage(c, A, B, dt, B, 1, st, col);
 }
 
@@ -494,6 +485,8 @@ int grim_set_prims(grim_ctx_t* c, const double* P, int on_device)
         src = c->interior;
     }
     HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, src, 0, c->P[c->cur], 1, c->st));
+    const int bc[3] = {c->cfg.bc[0], c->cfg.bc[1], c->cfg.bc[2]};
+    HIP_TRY(c, grim::launch_fill_ghosts(c->L, c->nvar, bc, c->P[c->cur], c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     return GRIM_OK;
 }

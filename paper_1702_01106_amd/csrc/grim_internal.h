@@ -105,6 +105,11 @@ struct NewtonArgs {
     // 0: one solve; 1: FP32 pass that marks failed zones kFlagRetry instead
     // of counting them; 2: FP64 solve from P_n of the marked zones only
     int pass;
+    // with out_ghosted: also write every ghost cell whose boundary map
+    // (bc per direction: 0 periodic, 1 outflow, 2 polar) takes its value from
+    // this zone, so the output needs no separate ghost fill
+    int write_ghosts;
+    int bc[3];
 };
 constexpr uint8_t kFlagRetry = 32;
 
@@ -112,7 +117,6 @@ constexpr uint8_t kFlagRetry = 32;
 hipError_t launch_fill_ghosts(const Layout& L, int nvar, const int bc[3], double* P, hipStream_t st);
 hipError_t launch_explicit_stage(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t st);
-hipError_t launch_emf(const StageArgs& a, hipStream_t st);
 hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st);
 hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const double* P, double* R, double* rnorm,

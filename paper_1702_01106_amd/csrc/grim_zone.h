@@ -91,13 +91,22 @@ __device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G
     }
 }
 
-// sum of squares of a residual vector
+// The Newton system (Sec. 8.2: 5x5 for ideal MHD, 7x7 for EMHD) is over the
+// non-magnetic primitives; B stays at its explicit update, the root of the
+// induction rows, which depend on B alone.  Unknown i is primitive unk(i).
+template <int NV>
+struct Sys {
+    static constexpr int N = NV - 3;
+};
+__device__ __forceinline__ constexpr int unk(int i) { return i < B1 ? i : i + 3; }
+
+// sum of squares of the system rows of a residual vector (B rows excluded)
 template <int NV>
 __device__ __forceinline__ double sumsq(const double* R)
 {
     double s = R[0] * R[0];
 #pragma unroll
-    for (int v = 1; v < NV; ++v) s = fma(R[v], R[v], s);
+    for (int i = 1; i < Sys<NV>::N; ++i) s = fma(R[unk(i)], R[unk(i)], s);
     return s;
 }
 

@@ -59,17 +59,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_ghosts(Layout L, int nvar, int 
 
 // ------------------------------------------------------------------ fluxes
 
-// One thread per face on the low side of cell (i, j, k) in direction DIR.
-// Left/right states by generalized-minmod PLM of the four cells along DIR,
-// then LLF with c_max the largest |speed| of either state.
+// The face on the low side of cell (i, j, k) in direction DIR.  Left/right
+// states by generalized-minmod PLM of the four cells along DIR, then LLF with
+// c_max the largest |speed| of either state.
 template <int NV, class G, int DIR>
-__global__ __launch_bounds__(kBlock) void k_flux(StageArgs a, int lo0, int lo1, int lo2, int c0, int c1, int c2)
+__device__ __forceinline__ void face_flux(const StageArgs& a, int i, int j, int k)
 {
-    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (long)c0 * c1 * c2) return;
-    const int i = lo0 + (int)(t % c0);
-    const int j = lo1 + (int)((t / c0) % c1);
-    const int k = lo2 + (int)(t / ((long)c0 * c1));
     const Layout& L = a.L;
     const long m = L.cell(i, j, k);
     const long st = L.stride(DIR - 1);
@@ -101,33 +96,50 @@ __global__ __launch_bounds__(kBlock) void k_flux(StageArgs a, int lo0, int lo1, 
     }
 }
 
-// Flux-CT (Sec. 4.2): edge EMFs as the average of the four face B-fluxes
-// around each edge.  E3 on (i-1/2, j-1/2, k), E1 on (i, j-1/2, k-1/2), E2 on
-// (i-1/2, j, k-1/2); stored at cell (i, j, k).
-__global__ __launch_bounds__(kBlock) void k_emf(StageArgs a, int c0, int c1, int c2)
+// Face ranges of every active direction in one launch: blocks
+// [first[d], first[d + 1]) take the faces normal to direction d, so each
+// block (and wave) works on one direction.
+struct FaceRanges {
+    int lo[3][3], cnt[3][3];
+    unsigned first[4];
+};
+
+template <int NV, class G>
+__global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
 {
-    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (long)c0 * c1 * c2) return;
+    const unsigned b = blockIdx.x;
+    const int d = b < r.first[1] ? 0 : (b < r.first[2] ? 1 : 2);
+    const long t = (long)(b - r.first[d]) * kBlock + threadIdx.x;
+    const int* cnt = r.cnt[d];
+    const int* lo = r.lo[d];
+    if (t >= (long)cnt[0] * cnt[1] * cnt[2]) return;
+    const int i = lo[0] + (int)(t % cnt[0]);
+    const int j = lo[1] + (int)((t / cnt[0]) % cnt[1]);
+    const int k = lo[2] + (int)(t / ((long)cnt[0] * cnt[1]));
+    if (d == 0) face_flux<NV, G, 1>(a, i, j, k);
+    else if (d == 1) face_flux<NV, G, 2>(a, i, j, k);
+    else face_flux<NV, G, 3>(a, i, j, k);
+}
+
+// Flux-CT (Sec. 4.2): the edge EMF as the average of the four face B-fluxes
+// around the edge.  E (index e) at cell c: E3 on (i-1/2, j-1/2, k), E1 on
+// (i, j-1/2, k-1/2), E2 on (i-1/2, j, k-1/2).  Evaluated where the stage
+// right-hand side needs it, from the face fluxes.
+template <int E>
+__device__ __forceinline__ double edge_emf(const StageArgs& a, long c)
+{
     const Layout& L = a.L;
-    const int g0 = L.g[0], g1 = L.g[1], g2 = L.g[2];
-    const int i = g0 + (int)(t % c0);
-    const int j = g1 + (int)((t / c0) % c1);
-    const int k = g2 + (int)(t / ((long)c0 * c1));
-    const long m = L.cell(i, j, k);
     const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
     const long C = L.cells;
     const double* F1 = a.F[0];
     const double* F2 = a.F[1];
-    const bool in0 = i < g0 + L.n[0], in1 = j < g1 + L.n[1];
-    if (L.ndim == 2) {
-        a.E[2][m] = 0.25 * (F1[B2 * C + m] + F1[B2 * C + m - s2] - F2[B1 * C + m] - F2[B1 * C + m - s1]);
-        return;
-    }
     const double* F3 = a.F[2];
-    const bool in2 = k < g2 + L.n[2];
-    if (in2) a.E[2][m] = 0.25 * (F1[B2 * C + m] + F1[B2 * C + m - s2] - F2[B1 * C + m] - F2[B1 * C + m - s1]);
-    if (in0) a.E[0][m] = 0.25 * (F2[B3 * C + m] + F2[B3 * C + m - s3] - F3[B2 * C + m] - F3[B2 * C + m - s2]);
-    if (in1) a.E[1][m] = 0.25 * (F3[B1 * C + m] + F3[B1 * C + m - s1] - F1[B3 * C + m] - F1[B3 * C + m - s3]);
+    if constexpr (E == 2)
+        return 0.25 * (F1[B2 * C + c] + F1[B2 * C + c - s2] - F2[B1 * C + c] - F2[B1 * C + c - s1]);
+    else if constexpr (E == 0)
+        return 0.25 * (F2[B3 * C + c] + F2[B3 * C + c - s3] - F3[B2 * C + c] - F3[B2 * C + c - s2]);
+    else
+        return 0.25 * (F3[B1 * C + c] + F3[B1 * C + c - s1] - F1[B3 * C + c] - F1[B3 * C + c - s3]);
 }
 
 // ------------------------------------------------------------------ stage rhs
@@ -190,12 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
                 // face B^b flux through faces normal to d, from the edge EMFs
                 auto face = [&](long c) -> double {
                     if (b == d) return 0.0;
-                    if (d == 0 && b == 1) return 0.5 * (a.E[2][c] + a.E[2][c + s2]);
-                    if (d == 0 && b == 2) return -0.5 * (a.E[1][c] + a.E[1][c + s3]);
-                    if (d == 1 && b == 0) return -0.5 * (a.E[2][c] + a.E[2][c + s1]);
-                    if (d == 1 && b == 2) return 0.5 * (a.E[0][c] + a.E[0][c + s3]);
-                    if (d == 2 && b == 0) return 0.5 * (a.E[1][c] + a.E[1][c + s1]);
-                    return -0.5 * (a.E[0][c] + a.E[0][c + s2]);  // d == 2 && b == 1
+                    if (d == 0 && b == 1) return 0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s2));
+                    if (d == 0 && b == 2) return -0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s3));
+                    if (d == 1 && b == 0) return -0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s1));
+                    if (d == 1 && b == 2) return 0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s3));
+                    if (d == 2 && b == 0) return 0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s1));
+                    return -0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s2));  // d == 2 && b == 1
                 };
                 fr = face(m + st);
                 fl = face(m);
@@ -515,35 +527,21 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
     const int nd = L.ndim;
     // face ranges: along d the n_d + 1 faces of interior cells; across the
     // other active directions one extra row each side (flux-CT needs them)
-    for (int d = 0; d < nd; ++d) {
-        int lo[3], cnt[3];
+    FaceRanges r{};
+    unsigned blocks = 0;
+    for (int d = 0; d < 3; ++d) {
+        r.first[d] = blocks;
+        if (d >= nd) continue;
         for (int e = 0; e < 3; ++e) {
-            if (e == d) { lo[e] = L.g[e]; cnt[e] = L.n[e] + 1; }
-            else if (e < nd) { lo[e] = L.g[e] - 1; cnt[e] = L.n[e] + 2; }
-            else { lo[e] = 0; cnt[e] = 1; }
+            if (e == d) { r.lo[d][e] = L.g[e]; r.cnt[d][e] = L.n[e] + 1; }
+            else if (e < nd) { r.lo[d][e] = L.g[e] - 1; r.cnt[d][e] = L.n[e] + 2; }
+            else { r.lo[d][e] = 0; r.cnt[d][e] = 1; }
         }
-        const long n = (long)cnt[0] * cnt[1] * cnt[2];
-        if (d == 0)
-            hipLaunchKernelGGL((k_flux<NV, G, 1>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
-                               cnt[0], cnt[1], cnt[2]);
-        else if (d == 1)
-            hipLaunchKernelGGL((k_flux<NV, G, 2>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
-                               cnt[0], cnt[1], cnt[2]);
-        else
-            hipLaunchKernelGGL((k_flux<NV, G, 3>), dim3(nblocks(n)), dim3(kBlock), 0, st, a, lo[0], lo[1], lo[2],
-                               cnt[0], cnt[1], cnt[2]);
+        blocks += nblocks((long)r.cnt[d][0] * r.cnt[d][1] * r.cnt[d][2]);
     }
-    return hipGetLastError();
-}
-
-hipError_t emf_t(const StageArgs& a, hipStream_t st)
-{
-    const Layout& L = a.L;
-    const int nd = L.ndim;
-    if (nd >= 2) {
-        const int c0 = L.n[0] + 1, c1 = L.n[1] + 1, c2 = nd == 3 ? L.n[2] + 1 : 1;
-        hipLaunchKernelGGL(k_emf, dim3(nblocks((long)c0 * c1 * c2)), dim3(kBlock), 0, st, a, c0, c1, c2);
-    }
+    r.first[3] = blocks;
+    for (int d = nd; d < 3; ++d) r.first[d] = blocks;
+    hipLaunchKernelGGL((k_fluxes<NV, G>), dim3(blocks), dim3(kBlock), 0, st, a, r);
     return hipGetLastError();
 }
 
@@ -561,7 +559,6 @@ template <int NV, class G>
 hipError_t explicit_stage_t(const StageArgs& a, hipStream_t st)
 {
     hipError_t e = fluxes_t<NV, G>(a, st);
-    if (e == hipSuccess) e = emf_t(a, st);
     if (e == hipSuccess) e = rhs_t<NV, G>(a, st);
     return e;
 }
@@ -585,8 +582,6 @@ hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t s
     if (nvar == 8) return metric == 0 ? fluxes_t<8, GeoMink>(a, st) : fluxes_t<8, GeoKS>(a, st);
     return metric == 0 ? fluxes_t<10, GeoMink>(a, st) : fluxes_t<10, GeoKS>(a, st);
 }
-
-hipError_t launch_emf(const StageArgs& a, hipStream_t st) { return emf_t(a, st); }
 
 hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st)
 {

@@ -119,9 +119,107 @@ __device__ __forceinline__ void Pc_from_net(const double* pn, const float* y, do
     }
 }
 
+// The Newton direction dP (zero in the B entries) at P, whose residual is R:
+// the finite-difference Jacobian over the system's unknowns, column by
+// column, then LU with partial pivoting.  Returns false on an exactly zero
+// pivot.
+template <int NV, class G, typename JT>
+__device__ __forceinline__ bool newton_dir(const double* P, const double* R, const ZoneC<NV, G>& zc,
+                                           const Phys& ph, double eps, double* dP)
+{
+    constexpr int N = Sys<NV>::N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dP[v] = 0.0;
+    JT J[N][N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double Pe[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Pe[q] = P[q];
+        const double pj = P[unk(j)];
+        const bool small = fabs(pj) < 5.0 * eps;
+        double pe = small ? eps : (1.0 + eps) * pj;
+        double h = pe - pj;
+        if (h == 0.0) {
+            pe = pj + eps;
+            h = pe - pj;
+        }
+        Pe[unk(j)] = pe;
+        double Re[NV];
+        zone_residual<NV, G>(Pe, zc, ph, Re);
+        const double ih = 1.0 / h;
+#pragma unroll
+        for (int i = 0; i < N; ++i) J[i][j] = (JT)((Re[unk(i)] - R[unk(i)]) * ih);
+    }
+    JT x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = (JT)(-R[unk(i)]);
+    if (!lu_solve<N, JT>(J, x)) return false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) dP[unk(i)] = (double)x[i];
+    return true;
+}
+
+// Ghosted coordinates along one direction that take their value from
+// interior index p (p itself first): the inverses of the ghost maps
+// (periodic wrap, outflow clamp, polar mirror, Ng = 2).  Returns the count;
+// mirror[m] marks a polar image.
+__device__ __forceinline__ int ghost_images(int p, int g, int n, int bc, int* q, bool* mirror)
+{
+    int c = 0;
+    q[c] = p;
+    mirror[c++] = false;
+    if (bc == 0) {
+        if (p >= n) { q[c] = p - n; mirror[c++] = false; }          // lower ghost p - n in [0, g)
+        if (p < 2 * g) { q[c] = p + n; mirror[c++] = false; }       // upper ghost in [g + n, 2g + n)
+    } else if (bc == 1) {
+        if (p == g)
+            for (int m = 0; m < g; ++m) { q[c] = m; mirror[c++] = false; }
+        if (p == g + n - 1)
+            for (int m = 0; m < g; ++m) { q[c] = g + n + m; mirror[c++] = false; }
+    } else {
+        if (p < 2 * g) { q[c] = 2 * g - 1 - p; mirror[c++] = true; }
+        if (p >= n) { q[c] = 2 * (g + n) - 1 - p; mirror[c++] = true; }
+    }
+    return c;
+}
+
+// Store a zone's primitives at its cell and at every ghost cell that maps to
+// it (the composite map is the product of the per-direction maps; a polar
+// image in X2 negates utilde^2 and B^2).
+template <int NV>
+__device__ __forceinline__ void store_with_ghosts(const Layout& L, const int* bc, long z, const double* P, double* out)
+{
+    const int p[3] = {(int)(z % L.n[0]) + L.g[0], (int)((z / L.n[0]) % L.n[1]) + L.g[1],
+                      (int)(z / ((long)L.n[0] * L.n[1])) + L.g[2]};
+    int q[3][5];
+    bool mir[3][5];
+    int cnt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d < L.ndim) {
+            cnt[d] = ghost_images(p[d], L.g[d], L.n[d], bc[d], q[d], mir[d]);
+        } else {
+            cnt[d] = 1;
+            q[d][0] = p[d];
+            mir[d][0] = false;
+        }
+    }
+    for (int c2 = 0; c2 < cnt[2]; ++c2)
+        for (int c1 = 0; c1 < cnt[1]; ++c1)
+            for (int c0 = 0; c0 < cnt[0]; ++c0) {
+                const long cell = L.cell(q[0][c0], q[1][c1], q[2][c2]);
+                const bool flip = mir[1][c1];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    out[(long)v * L.cells + cell] = (flip && (v == U2 || v == B2)) ? -P[v] : P[v];
+            }
+}
+
 template <int NV, class G, typename JT>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
+    constexpr int N = Sys<NV>::N;
     const long z = (long)blockIdx.x * kWave + threadIdx.x;
     const Layout& L = a.s.L;
     const bool retry = a.pass == 2;
@@ -200,43 +298,17 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
                 if (!isfinite(r)) { fl |= 16; break; }
                 if (r < a.tol) break;
                 if (k >= a.k_max) { fl |= 1; break; }
-                // finite-difference Jacobian, column by column
-                JT J[NV][NV];
-#pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    double Pe[NV];
-#pragma unroll
-                    for (int q = 0; q < NV; ++q) Pe[q] = P[q];
-                    const double pj = P[j];
-                    const bool small = fabs(pj) < 5.0 * eps;
-                    double pe = small ? eps : (1.0 + eps) * pj;
-                    double h = pe - pj;
-                    if (h == 0.0) {
-                        pe = pj + eps;
-                        h = pe - pj;
-                    }
-                    Pe[j] = pe;
-                    double Re[NV];
-                    zone_residual<NV, G>(Pe, zc, ph, Re);
-                    ++ncalls;
-                    const double ih = 1.0 / h;
-#pragma unroll
-                    for (int i = 0; i < NV; ++i) J[i][j] = (JT)((Re[i] - R[i]) * ih);
-                }
-                JT x[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) x[v] = (JT)(-R[v]);
-                if (!lu_solve<NV, JT>(J, x)) { fl |= 4; break; }
                 double dP[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dP[v] = (double)x[v];
+                const bool ok = newton_dir<NV, G, JT>(P, R, zc, ph, eps, dP);
+                ncalls += N;
+                if (!ok) { fl |= 4; break; }
 
                 // quadratic backtracking line search
                 const double f0 = r * r;
                 double lam = 1.0;
                 bool accepted = false, have = false;
                 double Pf[NV], Rf[NV], rf = 0.0;
-                for (int t = 0; t < a.ls_max; ++t) {
+                for (int tr = 0; tr < a.ls_max; ++tr) {
                     double Pt[NV], Rt[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], P[v]);
@@ -303,32 +375,37 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
             if (!(P[RHO] >= rf)) P[RHO] = rf;
             if (!(P[UU] >= uf)) P[UU] = uf;
         }
-        if (a.out_ghosted) {
+        {
+            if (a.out_ghosted && a.write_ghosts) {
+                store_with_ghosts<NV>(L, a.bc, z, P, a.out);
+            } else if (a.out_ghosted) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + cell] = P[v];
-        } else {
+                for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + cell] = P[v];
+            } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = P[v];
+                for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = P[v];
+            }
+            if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + iters;
+            if (a.resid) a.resid[z] = rr;
+            if (a.flags) a.flags[z] = fl;
         }
-        if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + iters;
-        if (a.resid) a.resid[z] = rr;
-        if (a.flags) a.flags[z] = fl;
     }
 
     // wave-level statistics, one atomic per wave.  A zone marked for the
-    // FP64 retry contributes only its work (iterations, residual calls) to
-    // the FP32 pass; the retry pass reports its outcome.
+    // FP64 retry contributes only its work (iterations, residual calls) to the
+    // FP32 pass; the retry pass reports its outcome.
     if (a.stats) {
-        const bool final_ = active && !(a.pass == 1 && (fl & kFlagRetry));
-        const double sit = wave_sum(active ? (double)iters : 0.0);
-        const int mit = wave_max(active ? iters : 0);
+        const bool mine = active;
+        const bool final_ = mine && !(a.pass == 1 && (fl & kFlagRetry));
+        const double sit = wave_sum(mine ? (double)iters : 0.0);
+        const int mit = wave_max(mine ? iters : 0);
         const double nf = wave_sum(final_ && (fl & (1 | 4 | 16)) ? 1.0 : 0.0);
         const double nl = wave_sum(final_ && (fl & 2) ? 1.0 : 0.0);
         const double nu = wave_sum(final_ && (fl & 8) ? 1.0 : 0.0);
-        const double na = wave_sum(active && !retry ? 1.0 : 0.0);
-        const double nc = wave_sum(active ? (double)ncalls : 0.0);
-        const double nfb = wave_sum(active ? (double)fallback : 0.0);
-        const double nrt = wave_sum(active && retry ? 1.0 : 0.0);
+        const double na = wave_sum(mine && !retry ? 1.0 : 0.0);
+        const double nc = wave_sum(mine ? (double)ncalls : 0.0);
+        const double nfb = wave_sum(mine ? (double)fallback : 0.0);
+        const double nrt = wave_sum(mine && retry ? 1.0 : 0.0);
         unsigned long long rb = 0;
         if (final_) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
         rb = wave_maxu64(rb);
