@@ -191,6 +191,37 @@ def variant_line(zones, steps, t, st, times, P_end, P_ref, value_ref):
     }
 
 
+def forms(grim, W, wl, P0, args, plain=None):
+    """Plain FP64, FP32 Jacobian, and both with the learned guess.  The
+    network is trained once (untimed) on pairs from FP64 runs of the same
+    workload on seeds 1-4 and evaluated on seed 0."""
+    import torch
+
+    from paper_1702_01106_amd import learned
+
+    zones = int(P0[0].size)
+    res = {}
+    if plain is None:
+        r = timed_run(grim, W, wl, P0, args.steps, args.warmup)
+        value_ref, P_ref = zones * args.steps / r[1], r[5]
+        res["f64"] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_ref, value_ref)
+    else:
+        value_ref, P_ref = plain
+    r = timed_run(grim, W, dict(wl, jac="f32"), P0, args.steps, args.warmup)
+    res["f32_jacobian"] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_ref, value_ref)
+    t0 = time.perf_counter()
+    w, info = learned.train_guess(wl, seeds=(1, 2, 3, 4), steps=wl["steps"], pairs=args.pairs, epochs=args.epochs,
+                                  batch=4096)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for name, jac in (("f64_learned_guess", "f64"), ("f32_jacobian_learned_guess", "f32")):
+        r = timed_run(grim, W, dict(wl, jac=jac, guess="mlp"), P0, args.steps, args.warmup, weights=w)
+        res[name] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_ref, value_ref)
+    res["training"] = {"pairs": info["pairs"], "epochs": args.epochs, "seconds": t_train,
+                       "loss_first_last": [info["loss"][0], info["loss"][-1]], "seeds": [1, 2, 3, 4]}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +233,8 @@ def main() -> int:
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--pairs", type=int, default=1_000_000, help="training pairs of the learned guess")
     ap.add_argument("--epochs", type=int, default=8, help="training epochs of the learned guess")
+    ap.add_argument("--variant-workloads", default="emhd2d_modes_512",
+                    help="comma-separated extra workloads for the four forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU halo exchange is not built",
@@ -264,23 +297,14 @@ def main() -> int:
     }
     out["stream"] = stream_probe(grim, wl)
     if not args.no_variants:
-        from paper_1702_01106_amd import learned
-
+        # the four forms (FP64 or FP32 Jacobian, P_n or learned guess) on this
+        # workload and on the learned-guess configuration (512^2), each against
+        # the plain FP64 form of the same workload
         variants = {}
-        r = timed_run(grim, W, dict(wl, jac="f32"), P0, args.steps, args.warmup)
-        variants["f32_jacobian_lu"] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_f64, value)
-        # learned guess: trained once on pairs from FP64 runs of the same
-        # workload on seeds 1-4 (untimed), evaluated on seed 0
-        t0 = time.perf_counter()
-        w, info = learned.train_guess(wl, seeds=(1, 2, 3, 4), steps=wl["steps"], pairs=args.pairs,
-                                      epochs=args.epochs, batch=4096)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - t0
-        for name, jac in (("learned_guess_f64", "f64"), ("learned_guess_f32_jacobian", "f32")):
-            r = timed_run(grim, W, dict(wl, jac=jac, guess="mlp"), P0, args.steps, args.warmup, weights=w)
-            variants[name] = variant_line(zones, args.steps, r[1], r[2], r[4], r[5], P_f64, value)
-        variants["training"] = {"pairs": info["pairs"], "epochs": args.epochs, "seconds": t_train,
-                                "loss_first_last": [info["loss"][0], info["loss"][-1]], "seeds": [1, 2, 3, 4]}
+        for vname in [args.workload] + [v for v in args.variant_workloads.split(",") if v and v != args.workload]:
+            vwl = W.workload(vname)
+            vP0 = P0 if vname == args.workload else W.initial_state(vwl, seed=0)
+            variants[vname] = forms(grim, W, vwl, vP0, args, None if vname != args.workload else (value, P_f64))
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, P0, dt, args.cpu_steps)

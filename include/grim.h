@@ -64,6 +64,7 @@ extern "C" {
 /* initial guess of the Newton solve */
 #define GRIM_GUESS_PN 0
 #define GRIM_GUESS_MLP 1
+
 /* learned-guess network: inputs, hidden width, outputs, parameter count */
 #define GRIM_MLP_IN 32
 #define GRIM_MLP_HIDDEN 128

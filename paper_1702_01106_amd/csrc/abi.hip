@@ -151,6 +151,7 @@ int validate(const grim_config_t* g, std::string& why)
     if (g->k_max < 0 || g->ls_max < 1) return why = "k_max >= 0 and ls_max >= 1 required", 1;
     if (g->jac_precision != GRIM_JAC_F64 && g->jac_precision != GRIM_JAC_F32) return why = "bad jac_precision", 1;
     if (g->guess != GRIM_GUESS_PN && g->guess != GRIM_GUESS_MLP) return why = "bad guess", 1;
+
     const double zones = (double)n[0] * n[1] * n[2];
     if (zones > 2.0e9) return why = "too many zones", 1;
     return 0;
@@ -427,7 +428,7 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     if (!rc) rc = dalloc(c, &c->iters, (size_t)L.nz);
     if (!rc) rc = dalloc(c, &c->resid, (size_t)L.nz);
     if (!rc) rc = dalloc(c, &c->flags, (size_t)L.nz);
-    if (!rc) rc = dalloc(c, &c->stats, 1);
+    if (!rc) rc = dalloc(c, &c->stats, (size_t)grim::kStatCopies);
     if (!rc) rc = dalloc(c, &c->u64, 4);
     if (!rc) rc = dalloc(c, &c->mlp_p, (size_t)grim::kMlpParams);
     if (!rc) rc = dalloc(c, &c->mlp_w[0], (size_t)grim::kMlpHidden * grim::kMlpIn);
@@ -567,9 +568,11 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
         }
     }
     if (stats) {
-        DevStats d{};
-        HIP_TRY(c, hipMemcpyAsync(&d, c->stats, sizeof(d), hipMemcpyDeviceToHost, c->st));
+        std::vector<DevStats> copies(grim::kStatCopies);
+        HIP_TRY(c, hipMemcpyAsync(copies.data(), c->stats, sizeof(DevStats) * grim::kStatCopies,
+                                  hipMemcpyDeviceToHost, c->st));
         HIP_TRY(c, hipStreamSynchronize(c->st));
+        const DevStats d = grim::sum_stats(copies.data(), grim::kStatCopies);
         const double per_stage = (double)c->L.nz * (double)(nsteps > 0 ? nsteps : 1);
         stats->mean_iters[0] = (double)d.iters[0] / per_stage;
         stats->mean_iters[1] = (double)d.iters[1] / per_stage;

@@ -25,14 +25,39 @@ struct Layout {
     __host__ __device__ long stride(int d) const { return d == 0 ? 1L : (d == 1 ? (long)N[0] : (long)N[0] * N[1]); }
 };
 
-// Device-side accumulators of the solver statistics.
-struct DevStats {
+// Device-side accumulators of the solver statistics.  kStatCopies copies,
+// one 128-byte line each: a wave adds into copy (block index mod copies), so
+// no address sees more than 1/kStatCopies of the waves' atomics (atomics to
+// one address serialise in its L2 channel, which cost more than the Newton
+// iterations themselves at 4,096 waves).  The host sums the copies.
+constexpr int kStatCopies = 256;
+struct alignas(128) DevStats {
     unsigned long long iters[2];
     unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback, n_retry;
     unsigned long long max_resid_bits;
     unsigned int max_iters;
     unsigned int pad;
 };
+
+// Sum (max for the maxima) of the statistics copies, on the host.
+inline DevStats sum_stats(const DevStats* s, int n)
+{
+    DevStats d{};
+    for (int i = 0; i < n; ++i) {
+        d.iters[0] += s[i].iters[0];
+        d.iters[1] += s[i].iters[1];
+        d.n_fail += s[i].n_fail;
+        d.n_ls += s[i].n_ls;
+        d.n_unphys += s[i].n_unphys;
+        d.zone_stages += s[i].zone_stages;
+        d.resid_calls += s[i].resid_calls;
+        d.n_fallback += s[i].n_fallback;
+        d.n_retry += s[i].n_retry;
+        d.max_resid_bits = s[i].max_resid_bits > d.max_resid_bits ? s[i].max_resid_bits : d.max_resid_bits;
+        d.max_iters = s[i].max_iters > d.max_iters ? s[i].max_iters : d.max_iters;
+    }
+    return d;
+}
 
 // Metric tables (Kerr-Schild only).  Centre and face tables depend on
 // (i, j) only: the metric is independent of X3.  Layout [kGeoDoubles][N2*N1];

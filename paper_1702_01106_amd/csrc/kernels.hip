@@ -456,11 +456,12 @@ __global__ __launch_bounds__(kBlock) void k_cfl(Layout L, Phys ph, GeoTables geo
 
 // ------------------------------------------------------------------ utilities
 
-// clears every field: the struct as 8-byte words, one lane per word
+// clears every field of every copy: block b takes copy b, as 8-byte words,
+// one lane per word
 __global__ void k_zero_stats(DevStats* s)
 {
     static_assert(sizeof(DevStats) % 8 == 0 && sizeof(DevStats) / 8 <= 64, "DevStats layout");
-    unsigned long long* w = reinterpret_cast<unsigned long long*>(s);
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(s + blockIdx.x);
     if (threadIdx.x < sizeof(DevStats) / 8) w[threadIdx.x] = 0ull;
 }
 
@@ -619,7 +620,7 @@ hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int
 
 hipError_t launch_zero_stats(DevStats* s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_zero_stats, dim3(kStatCopies), dim3(64), 0, st, s);
     return hipGetLastError();
 }
 

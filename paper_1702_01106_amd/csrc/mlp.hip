@@ -276,20 +276,31 @@ __global__ void k_out_grad(const float* __restrict__ O, const float* __restrict_
                            const float* __restrict__ TB, const float* __restrict__ dY, int nb, int n_used,
                            float inv_count, float* __restrict__ dO, double* __restrict__ loss)
 {
+    // launched with 256 threads per block; the loss is summed per block
+    // (wave shuffles, then LDS) and added with one atomic per block
+    __shared__ double part[4];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * DO) return;
-    const int j = t % DO;
-    float g = 0.0f;
-    if (dY) {
-        g = dY[t] * ys[j];
-    } else if (j < n_used && ys[j] != 0.0f) {
-        // loss in normalised output units: ((y - t) / y_scale)^2; an output
-        // with y_scale 0 is held at zero and carries no loss
-        const float d = (O[t] + b3[j]) - TB[t] / ys[j];
-        g = 2.0f * d * inv_count;
-        atomicAdd(loss, (double)d * (double)d * (double)inv_count);
+    double contrib = 0.0;
+    if (t < nb * DO) {
+        const int j = t % DO;
+        float g = 0.0f;
+        if (dY) {
+            g = dY[t] * ys[j];
+        } else if (j < n_used && ys[j] != 0.0f) {
+            // loss in normalised output units: ((y - t) / y_scale)^2; an output
+            // with y_scale 0 is held at zero and carries no loss
+            const float d = (O[t] + b3[j]) - TB[t] / ys[j];
+            g = 2.0f * d * inv_count;
+            contrib = (double)d * (double)d * (double)inv_count;
+        }
+        dO[t] = g;
     }
-    dO[t] = g;
+    if (dY) return;  // block-uniform
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = contrib;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
 }
 
 __global__ void k_gelu_back(float* __restrict__ dH, const float* __restrict__ Z, int count)

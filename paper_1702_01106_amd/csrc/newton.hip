@@ -216,222 +216,281 @@ __device__ __forceinline__ void store_with_ghosts(const Layout& L, const int* bc
             }
 }
 
+// Per-lane state of one zone's solve.
+template <int NV, class G>
+struct ZoneSolve {
+    ZoneC<NV, G> zc;
+    double P[NV], R[NV];
+    double r, nscale, fB;
+    long z, cell;
+    int k, iters, ncalls, fallback;
+    bool from_net;
+    uint8_t fl;
+};
+
+// Start zone z: load its constants, P_n (or the caller's guess) with B at its
+// explicit update (the exact root of the B rows), the learned candidate if one
+// is given and its residual is smaller, and the initial residual.
+template <int NV, class G>
+__device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const double* guess, const float* mlp_y,
+                                         ZoneSolve<NV, G>& s)
+{
+    const Layout& L = a.s.L;
+    const Phys& ph = a.s.ph;
+    s.z = z;
+    s.cell = zone_cell(L, z);
+    load_zone<NV, G>(a.s, z, s.cell, s.zc);
+    s.fB = a.s.dtp / s.zc.g.gdet();
+    s.k = 0;
+    s.iters = 0;
+    s.ncalls = 0;
+    s.fallback = 0;
+    s.from_net = false;
+    s.fl = 0;
+    double P_alt[NV];
+    {
+        double pn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * L.cells + s.cell];
+        St<NV> sn;
+        derive<NV>(pn, s.zc.g, ph, sn);
+        // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
+        s.nscale = a.s.dtp / (s.zc.g.gdet() * pn[RHO] * sn.ucon[0]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s.P[v] = guess ? guess[(long)v * L.nz + z] : pn[v];
+        if (mlp_y) Pc_from_net<NV>(pn, mlp_y + z * kMlpOut, P_alt);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
+    zone_residual<NV, G>(s.P, s.zc, ph, s.R);
+    ++s.ncalls;
+    s.r = s.nscale * sqrt(sumsq<NV>(s.R));
+    if (mlp_y) {
+        // keep the learned guess only if its residual is smaller
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P_alt[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
+        double Rc[NV];
+        zone_residual<NV, G>(P_alt, s.zc, ph, Rc);
+        ++s.ncalls;
+        const double rc = s.nscale * sqrt(sumsq<NV>(Rc));
+        if (rc < s.r) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                s.P[v] = P_alt[v];
+                s.R[v] = Rc[v];
+            }
+            s.r = rc;
+            s.from_net = true;
+        } else {
+            s.fallback = 1;
+        }
+    }
+}
+
+// One step of the solve: the convergence tests, then one Newton iteration
+// with its line search.  Returns true once the solve has ended (converged, or
+// failed with the flags set).  A failed solve from the learned guess starts
+// again from P_n instead of ending.
+template <int NV, class G, typename JT>
+__device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s)
+{
+    constexpr int N = Sys<NV>::N;
+    const Phys& ph = a.s.ph;
+    bool ended = false;
+    if (!isfinite(s.r)) {
+        s.fl |= 16;
+        ended = true;
+    } else if (s.r < a.tol) {
+        return true;
+    } else if (s.k >= a.k_max) {
+        s.fl |= 1;
+        ended = true;
+    } else {
+        double dP[NV];
+        const bool ok = newton_dir<NV, G, JT>(s.P, s.R, s.zc, ph, a.eps, dP);
+        s.ncalls += N;
+        if (!ok) {
+            s.fl |= 4;
+            ended = true;
+        } else {
+            // quadratic backtracking line search
+            const double r = s.r, f0 = r * r;
+            double lam = 1.0;
+            bool accepted = false, have = false;
+            double Pf[NV], Rf[NV], rf = 0.0;
+            for (int tr = 0; tr < a.ls_max; ++tr) {
+                double Pt[NV], Rt[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], s.P[v]);
+                zone_residual<NV, G>(Pt, s.zc, ph, Rt);
+                ++s.ncalls;
+                const double rt = s.nscale * sqrt(sumsq<NV>(Rt));
+                if (isfinite(rt)) {
+                    have = true;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        Pf[v] = Pt[v];
+                        Rf[v] = Rt[v];
+                    }
+                    rf = rt;
+                    if (rt < r * (1.0 - a.eps_bt * lam)) {
+                        accepted = true;
+                        break;
+                    }
+                    // minimiser of the quadratic model f(0) - 2 f(0) lam + c lam^2,
+                    // kept within [0.1, 0.5] of the previous lambda
+                    const double ln = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
+                    lam = fmin(fmax(ln, 0.1 * lam), 0.5 * lam);
+                } else {
+                    lam *= 0.5;
+                }
+            }
+            ++s.iters;
+            ++s.k;
+            if (!accepted) {
+                s.fl |= 2;
+                if (!have) {
+                    s.fl |= 16;
+                    ended = true;
+                }
+            }
+            if (have) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    s.P[v] = Pf[v];
+                    s.R[v] = Rf[v];
+                }
+                s.r = rf;
+            }
+        }
+    }
+    if (!ended) return false;
+    if (!(s.from_net && (s.fl & (1 | 4 | 16)))) return true;
+    // the solve from the learned guess failed: start again from P_n
+    const Layout& L = a.s.L;
+    s.from_net = false;
+    s.fallback = 1;
+    s.fl = 0;
+    s.k = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s.P[v] = a.s.Pn[(long)v * L.cells + s.cell];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
+    zone_residual<NV, G>(s.P, s.zc, ph, s.R);
+    ++s.ncalls;
+    s.r = s.nscale * sqrt(sumsq<NV>(s.R));
+    return false;
+}
+
+// Per-lane accumulators of the statistics over the zones a lane finishes.
+struct LaneStats {
+    double iters = 0, nf = 0, nl = 0, nu = 0, na = 0, nc = 0, nfb = 0, nrt = 0;
+    int mit = 0;
+    unsigned long long rb = 0;
+};
+
+// Floors, flags, outputs and statistics of a finished zone.
+template <int NV, class G>
+__device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>& s, bool retry, LaneStats& ls)
+{
+    const Layout& L = a.s.L;
+    const long z = s.z;
+    if (!(s.P[RHO] > 0.0) || !(s.P[UU] > 0.0)) s.fl |= 8;
+    if ((a.pass == 1 && (s.fl & (1 | 4 | 16))) || retry) s.fl |= kFlagRetry;
+    if (a.s.floors) {
+        const int ii = (int)(z % L.n[0]);
+        const double r1 = exp(L.xs[0] + (ii + 0.5) * L.dx[0]);
+        const double rf = a.s.rho_fl * pow(r1, -1.5), uf = a.s.u_fl * pow(r1, -2.5);
+        if (!(s.P[RHO] >= rf)) s.P[RHO] = rf;
+        if (!(s.P[UU] >= uf)) s.P[UU] = uf;
+    }
+    if (a.out_ghosted && a.write_ghosts) {
+        store_with_ghosts<NV>(L, a.bc, z, s.P, a.out);
+    } else if (a.out_ghosted) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + s.cell] = s.P[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = s.P[v];
+    }
+    if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + s.iters;
+    if (a.resid) a.resid[z] = s.r;
+    if (a.flags) a.flags[z] = s.fl;
+    // a zone marked for the FP64 retry contributes only its work (iterations,
+    // residual calls) to the FP32 pass; the retry pass reports its outcome
+    const bool final_ = !(a.pass == 1 && (s.fl & kFlagRetry));
+    ls.iters += s.iters;
+    ls.mit = max(ls.mit, s.iters);
+    ls.nc += s.ncalls;
+    ls.nfb += s.fallback;
+    if (!retry) ls.na += 1.0;
+    else ls.nrt += 1.0;
+    if (final_) {
+        if (s.fl & (1 | 4 | 16)) ls.nf += 1.0;
+        if (s.fl & 2) ls.nl += 1.0;
+        if (s.fl & 8) ls.nu += 1.0;
+        const unsigned long long b =
+            isfinite(s.r) ? (unsigned long long)__double_as_longlong(s.r) : 0x7FF0000000000000ull;
+        ls.rb = b > ls.rb ? b : ls.rb;
+    }
+}
+
+// Wave reduction of the lane statistics, one atomic per wave and counter.
+__device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats& ls)
+{
+    const double sit = wave_sum(ls.iters);
+    const int mit = wave_max(ls.mit);
+    const double nf = wave_sum(ls.nf), nl = wave_sum(ls.nl), nu = wave_sum(ls.nu);
+    const double na = wave_sum(ls.na), nc = wave_sum(ls.nc), nfb = wave_sum(ls.nfb), nrt = wave_sum(ls.nrt);
+    const unsigned long long rb = wave_maxu64(ls.rb);
+    DevStats* ds = a.stats + (blockIdx.x & (kStatCopies - 1));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&ds->iters[a.stage], (unsigned long long)sit);
+        atomicMax(&ds->max_iters, (unsigned)mit);
+        if (nf > 0) atomicAdd(&ds->n_fail, (unsigned long long)nf);
+        if (nl > 0) atomicAdd(&ds->n_ls, (unsigned long long)nl);
+        if (nu > 0) atomicAdd(&ds->n_unphys, (unsigned long long)nu);
+        if (na > 0) atomicAdd(&ds->zone_stages, (unsigned long long)na);
+        if (nrt > 0) atomicAdd(&ds->n_retry, (unsigned long long)nrt);
+        atomicAdd(&ds->resid_calls, (unsigned long long)nc);
+        if (nfb > 0) atomicAdd(&ds->n_fallback, (unsigned long long)nfb);
+        atomicMax(&ds->max_resid_bits, rb);
+    }
+}
+
+// A zone per lane: the wave runs until its slowest zone has finished.  (A
+// work-queue variant, where a lane that finished took the next zone of its
+// wave's range, ran 20-45% slower on every workload measured and was
+// dropped.)
 template <int NV, class G, typename JT>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
-    constexpr int N = Sys<NV>::N;
     const long z = (long)blockIdx.x * kWave + threadIdx.x;
-    const Layout& L = a.s.L;
     const bool retry = a.pass == 2;
-    bool active = z < L.nz;
+    bool active = z < a.s.L.nz;
     if (retry) {
         active = active && (a.flags[z] & kFlagRetry);
         if (__ballot(active) == 0ull) return;  // wave-uniform exit
     }
-    const double* guess = retry ? nullptr : a.guess;
-    const float* mlp_y = retry ? nullptr : a.mlp_y;
-    int iters = 0, ncalls = 0, fallback = 0;
-    uint8_t fl = 0;
-    double rr = 0.0;
-
+    LaneStats ls;
     if (active) {
-        const long cell = zone_cell(L, z);
-        ZoneC<NV, G> zc;
-        load_zone<NV, G>(a.s, z, cell, zc);
-        const Phys& ph = a.s.ph;
-        double P_alt[NV];
-
-        // initial guess: P_n (or the caller's guess) with B at its explicit
-        // update, the exact root of the B rows
-        const double fB = a.s.dtp / zc.g.gdet();
-        double P[NV];
-        double nscale;
-        {
-            double pn[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * L.cells + cell];
-            St<NV> sn;
-            derive<NV>(pn, zc.g, ph, sn);
-            // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
-            nscale = a.s.dtp / (zc.g.gdet() * pn[RHO] * sn.ucon[0]);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) P[v] = guess ? guess[(long)v * L.nz + z] : pn[v];
-            if (mlp_y) {
-                // learned candidate: P = P_n + scaled network output
-                const float* y = mlp_y + z * kMlpOut;
-                Pc_from_net<NV>(pn, y, P_alt);
-            }
+        ZoneSolve<NV, G> s;
+        zs_begin<NV, G>(a, z, retry ? nullptr : a.guess, retry ? nullptr : a.mlp_y, s);
+        while (!zs_step<NV, G, JT>(a, s)) {
         }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * fB;
-
-        double R[NV];
-        zone_residual<NV, G>(P, zc, ph, R);
-        ++ncalls;
-        double r = nscale * sqrt(sumsq<NV>(R));
-        bool from_net = false;
-        if (mlp_y) {
-            // keep the learned guess only if its residual is smaller
-#pragma unroll
-            for (int i = 0; i < 3; ++i) P_alt[B1 + i] = zc.rhs[B1 + i] * fB;
-            double Rc[NV];
-            zone_residual<NV, G>(P_alt, zc, ph, Rc);
-            ++ncalls;
-            const double rc = nscale * sqrt(sumsq<NV>(Rc));
-            if (rc < r) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    P[v] = P_alt[v];
-                    R[v] = Rc[v];
-                }
-                r = rc;
-                from_net = true;
-            } else {
-                fallback = 1;
-            }
-        }
-        const double eps = a.eps;
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            fl = 0;
-            int k = 0;
-            for (;;) {
-                if (!isfinite(r)) { fl |= 16; break; }
-                if (r < a.tol) break;
-                if (k >= a.k_max) { fl |= 1; break; }
-                double dP[NV];
-                const bool ok = newton_dir<NV, G, JT>(P, R, zc, ph, eps, dP);
-                ncalls += N;
-                if (!ok) { fl |= 4; break; }
-
-                // quadratic backtracking line search
-                const double f0 = r * r;
-                double lam = 1.0;
-                bool accepted = false, have = false;
-                double Pf[NV], Rf[NV], rf = 0.0;
-                for (int tr = 0; tr < a.ls_max; ++tr) {
-                    double Pt[NV], Rt[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], P[v]);
-                    zone_residual<NV, G>(Pt, zc, ph, Rt);
-                    ++ncalls;
-                    const double rt = nscale * sqrt(sumsq<NV>(Rt));
-                    if (isfinite(rt)) {
-                        have = true;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            Pf[v] = Pt[v];
-                            Rf[v] = Rt[v];
-                        }
-                        rf = rt;
-                        if (rt < r * (1.0 - a.eps_bt * lam)) {
-                            accepted = true;
-                            break;
-                        }
-                        // minimiser of the quadratic model f(0) - 2 f(0) lam + c lam^2,
-                        // kept within [0.1, 0.5] of the previous lambda
-                        const double ln = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
-                        lam = fmin(fmax(ln, 0.1 * lam), 0.5 * lam);
-                    } else {
-                        lam *= 0.5;
-                    }
-                }
-                if (!accepted) {
-                    fl |= 2;
-                    if (!have) {
-                        fl |= 16;
-                        ++iters;
-                        ++k;
-                        break;
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    P[v] = Pf[v];
-                    R[v] = Rf[v];
-                }
-                r = rf;
-                ++iters;
-                ++k;
-            }
-            if (!(from_net && (fl & (1 | 4 | 16)))) break;
-            // the solve from the learned guess failed: start again from P_n
-            from_net = false;
-            fallback = 1;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) P[v] = a.s.Pn[(long)v * L.cells + cell];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) P[B1 + i] = zc.rhs[B1 + i] * fB;
-            zone_residual<NV, G>(P, zc, ph, R);
-            ++ncalls;
-            r = nscale * sqrt(sumsq<NV>(R));
-        }
-        rr = r;
-        if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= 8;
-        if ((a.pass == 1 && (fl & (1 | 4 | 16))) || retry) fl |= kFlagRetry;
-        if (a.s.floors) {
-            const int ii = (int)(z % L.n[0]);
-            const double r1 = exp(L.xs[0] + (ii + 0.5) * L.dx[0]);
-            const double rf = a.s.rho_fl * pow(r1, -1.5), uf = a.s.u_fl * pow(r1, -2.5);
-            if (!(P[RHO] >= rf)) P[RHO] = rf;
-            if (!(P[UU] >= uf)) P[UU] = uf;
-        }
-        {
-            if (a.out_ghosted && a.write_ghosts) {
-                store_with_ghosts<NV>(L, a.bc, z, P, a.out);
-            } else if (a.out_ghosted) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + cell] = P[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = P[v];
-            }
-            if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + iters;
-            if (a.resid) a.resid[z] = rr;
-            if (a.flags) a.flags[z] = fl;
-        }
+        zs_finish<NV, G>(a, s, retry, ls);
     }
-
-    // wave-level statistics, one atomic per wave.  A zone marked for the
-    // FP64 retry contributes only its work (iterations, residual calls) to the
-    // FP32 pass; the retry pass reports its outcome.
-    if (a.stats) {
-        const bool mine = active;
-        const bool final_ = mine && !(a.pass == 1 && (fl & kFlagRetry));
-        const double sit = wave_sum(mine ? (double)iters : 0.0);
-        const int mit = wave_max(mine ? iters : 0);
-        const double nf = wave_sum(final_ && (fl & (1 | 4 | 16)) ? 1.0 : 0.0);
-        const double nl = wave_sum(final_ && (fl & 2) ? 1.0 : 0.0);
-        const double nu = wave_sum(final_ && (fl & 8) ? 1.0 : 0.0);
-        const double na = wave_sum(mine && !retry ? 1.0 : 0.0);
-        const double nc = wave_sum(mine ? (double)ncalls : 0.0);
-        const double nfb = wave_sum(mine ? (double)fallback : 0.0);
-        const double nrt = wave_sum(mine && retry ? 1.0 : 0.0);
-        unsigned long long rb = 0;
-        if (final_) rb = isfinite(rr) ? (unsigned long long)__double_as_longlong(rr) : 0x7FF0000000000000ull;
-        rb = wave_maxu64(rb);
-        if (threadIdx.x == 0) {
-            atomicAdd(&a.stats->iters[a.stage], (unsigned long long)sit);
-            atomicMax(&a.stats->max_iters, (unsigned)mit);
-            if (nf > 0) atomicAdd(&a.stats->n_fail, (unsigned long long)nf);
-            if (nl > 0) atomicAdd(&a.stats->n_ls, (unsigned long long)nl);
-            if (nu > 0) atomicAdd(&a.stats->n_unphys, (unsigned long long)nu);
-            if (na > 0) atomicAdd(&a.stats->zone_stages, (unsigned long long)na);
-            if (nrt > 0) atomicAdd(&a.stats->n_retry, (unsigned long long)nrt);
-            atomicAdd(&a.stats->resid_calls, (unsigned long long)nc);
-            if (nfb > 0) atomicAdd(&a.stats->n_fallback, (unsigned long long)nfb);
-            atomicMax(&a.stats->max_resid_bits, rb);
-        }
-    }
+    if (a.stats) flush_stats(a, ls);
 }
 
 template <int NV, class G>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
+    NewtonArgs b = a;
     if (jac_f32) {
         // FP32 pass, then the FP64 retry of the zones it marks (needs flags)
         if (!a.flags) return hipErrorInvalidValue;
-        NewtonArgs b = a;
         b.pass = 1;
         hipLaunchKernelGGL((k_newton<NV, G, float>), grid, blk, 0, st, b);
         const hipError_t e = hipGetLastError();
@@ -439,7 +498,6 @@ hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
         b.pass = 2;
         hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
     } else {
-        NewtonArgs b = a;
         b.pass = 0;
         hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
     }
