@@ -91,6 +91,18 @@ __device__ __forceinline__ float gelu_fast(float z)
     return 0.5f * z * (1.0f + copysignf(e, z));
 }
 
+// Four floats to bfloat16, round to nearest even: v_cvt_pk_bf16_f32 on gfx950
+// (two values per instruction).
+typedef __bf16 bfv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
+{
+    const fv2 lo = {a, b}, hi = {c, d};
+    const unsigned l = __builtin_bit_cast(unsigned, __builtin_convertvector(lo, bfv2));
+    const unsigned u = __builtin_bit_cast(unsigned, __builtin_convertvector(hi, bfv2));
+    return __builtin_bit_cast(bf16x4, (unsigned long long)l | ((unsigned long long)u << 32));
+}
+
 __device__ __forceinline__ bf16x4 lds_a(const unsigned short* base)
 {
     // 8-byte aligned: every row stride and k offset is a multiple of 4 elements
@@ -155,10 +167,8 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_mlp_infer(const float* __res
         for (int s = 0; s < DI / 8; ++s) {
             const int k0 = 8 * s + 4 * h;
             float4 x = live ? *reinterpret_cast<const float4*>(X + row * DI + k0) : make_float4(0.f, 0.f, 0.f, 0.f);
-            bx[s][0] = (short)to_bf16((x.x - sXm[k0 + 0]) * sXs[k0 + 0]);
-            bx[s][1] = (short)to_bf16((x.y - sXm[k0 + 1]) * sXs[k0 + 1]);
-            bx[s][2] = (short)to_bf16((x.z - sXm[k0 + 2]) * sXs[k0 + 2]);
-            bx[s][3] = (short)to_bf16((x.w - sXm[k0 + 3]) * sXs[k0 + 3]);
+            bx[s] = pack4((x.x - sXm[k0 + 0]) * sXs[k0 + 0], (x.y - sXm[k0 + 1]) * sXs[k0 + 1],
+                          (x.z - sXm[k0 + 2]) * sXs[k0 + 2], (x.w - sXm[k0 + 3]) * sXs[k0 + 3]);
         }
         bf16x4 b2[DH / 8];
 #pragma unroll
@@ -169,12 +179,11 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_mlp_infer(const float* __res
                 acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(lds_a(&sW1[(32 * t + c) * kS1 + 8 * s + 4 * h]), bx[s],
                                                               acc, 0, 0, 0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int m = 32 * t + 8 * q + 4 * h + e;
-                    b2[4 * t + q][e] = (short)to_bf16(gelu_fast(acc[4 * q + e] + sB1[m]));
-                }
+            for (int q = 0; q < 4; ++q) {
+                const int m = 32 * t + 8 * q + 4 * h;
+                b2[4 * t + q] = pack4(gelu_fast(acc[4 * q + 0] + sB1[m + 0]), gelu_fast(acc[4 * q + 1] + sB1[m + 1]),
+                                      gelu_fast(acc[4 * q + 2] + sB1[m + 2]), gelu_fast(acc[4 * q + 3] + sB1[m + 3]));
+            }
         }
         // ---- layer 2: k-steps outer, the four output tiles inner
         f32x16 acc2[DH / 32];
@@ -190,12 +199,11 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_mlp_infer(const float* __res
 #pragma unroll
         for (int t = 0; t < DH / 32; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int m = 32 * t + 8 * q + 4 * h + e;
-                    b3[4 * t + q][e] = (short)to_bf16(gelu_fast(acc2[t][4 * q + e] + sB2[m]));
-                }
+            for (int q = 0; q < 4; ++q) {
+                const int m = 32 * t + 8 * q + 4 * h;
+                b3[4 * t + q] = pack4(gelu_fast(acc2[t][4 * q + 0] + sB2[m + 0]), gelu_fast(acc2[t][4 * q + 1] + sB2[m + 1]),
+                                      gelu_fast(acc2[t][4 * q + 2] + sB2[m + 2]), gelu_fast(acc2[t][4 * q + 3] + sB2[m + 3]));
+            }
         // ---- layer 3: 32 output rows of which the first 16 are real
         f32x16 acc = {};
 #pragma unroll
