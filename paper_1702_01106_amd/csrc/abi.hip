@@ -157,6 +157,9 @@ int validate(const grim_config_t* g, std::string& why)
     return 0;
 }
 
+// Whether stage solves compute the right-hand side inside the Newton kernel.
+bool fused_rhs(const grim_ctx* c) { return c->cfg.metric == GRIM_MINKOWSKI; }
+
 StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)
 {
     StageArgs a{};
@@ -236,17 +239,16 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     StageArgs s = stage_args(c, Pn, PE, dtp);
     const bool net = c->cfg.guess == GRIM_GUESS_MLP && !col;
     if (net || col) s.mlp_x = c->mlp_x;
-    if (c->timing) {
-        {
-            Timed t(c, 1, st);
-            HIP_TRY(c, grim::launch_fluxes(s, c->nvar, c->cfg.metric, st));
-        }
-        {
-            Timed t(c, 3, st);
-            HIP_TRY(c, grim::launch_rhs(s, c->nvar, c->cfg.metric, st));
-        }
-    } else {
-        HIP_TRY(c, grim::launch_explicit_stage(s, c->nvar, c->cfg.metric, st));
+    // Minkowski without the network's features: the Newton kernel computes
+    // each zone's right-hand side itself (no rhs kernel, no rhs round trip)
+    const bool fused = fused_rhs(c) && !net && !col;
+    {
+        Timed t(c, 1, st);
+        HIP_TRY(c, grim::launch_fluxes(s, c->nvar, c->cfg.metric, st));
+    }
+    if (!fused) {
+        Timed t(c, 3, st);
+        HIP_TRY(c, grim::launch_rhs(s, c->nvar, c->cfg.metric, st));
     }
     if (net) {
         Timed t(c, 5, st);
@@ -256,6 +258,7 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     n.out = out;
     n.out_ghosted = 1;
     n.write_ghosts = 1;  // the output's ghosts are written with it
+    n.fused = fused ? 1 : 0;
     n.stage = stage;
     n.mlp_y = net ? c->mlp_y : nullptr;
     {
@@ -618,6 +621,7 @@ int grim_stage_solve(grim_ctx_t* c, const double* Pn, const double* PE, double d
     n.guess = guess;
     n.out = P_out;
     n.out_ghosted = 0;
+    n.fused = fused_rhs(c) ? 1 : 0;  // the same Newton kernel grim_run uses
     n.stage = 0;
     if (iters) n.iters = iters;
     if (resid) n.resid = resid;

@@ -135,6 +135,10 @@ struct NewtonArgs {
     // this zone, so the output needs no separate ghost fill
     int write_ghosts;
     int bc[3];
+    // 1: compute each zone's stage right-hand side in the Newton kernel from
+    // the face fluxes (fused), instead of reading what the rhs kernel stored
+    // (Minkowski only; ignored for Kerr)
+    int fused;
 };
 constexpr uint8_t kFlagRetry = 32;
 

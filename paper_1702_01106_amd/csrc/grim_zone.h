@@ -64,6 +64,27 @@ __device__ __forceinline__ void load_zone(const StageArgs& a, long z, long cell,
     }
 }
 
+// ZoneC from a zone's stage right-hand side and EMHD coefficients computed in
+// registers (the same fields load_zone reads from memory).
+template <int NV, class G>
+__device__ __forceinline__ void zone_from_rhs(const StageArgs& a, const double* co, ZoneC<NV, G>& zc)
+{
+    zc.idt = 1.0 / a.dtp;
+    if constexpr (NV == 10) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) zc.bh[m] = co[m];
+        zc.thn = co[4];
+        zc.u0n = co[5];
+        zc.cbun = co[6];
+        zc.aq1 = co[7];
+        zc.aq2 = co[8];
+        zc.aq3 = co[9];
+        zc.ad2 = co[10];
+        zc.ad3 = co[11];
+        zc.chalf = co[12];
+    }
+}
+
 template <int NV, class G>
 __device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G>& zc, const Phys& ph, double* R)
 {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "grim_internal.h"
+#include "grim_rhs.h"
 #include "grim_zone.h"
 
 namespace grim {
@@ -121,278 +122,22 @@ __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
     else face_flux<NV, G, 3>(a, i, j, k);
 }
 
-// Flux-CT (Sec. 4.2): the edge EMF as the average of the four face B-fluxes
-// around the edge.  E (index e) at cell c: E3 on (i-1/2, j-1/2, k), E1 on
-// (i, j-1/2, k-1/2), E2 on (i-1/2, j, k-1/2).  Evaluated where the stage
-// right-hand side needs it, from the face fluxes.
-template <int E>
-__device__ __forceinline__ double edge_emf(const StageArgs& a, long c)
-{
-    const Layout& L = a.L;
-    const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
-    const long C = L.cells;
-    const double* F1 = a.F[0];
-    const double* F2 = a.F[1];
-    const double* F3 = a.F[2];
-    if constexpr (E == 2)
-        return 0.25 * (F1[B2 * C + c] + F1[B2 * C + c - s2] - F2[B1 * C + c] - F2[B1 * C + c - s1]);
-    else if constexpr (E == 0)
-        return 0.25 * (F2[B3 * C + c] + F2[B3 * C + c - s3] - F3[B2 * C + c] - F3[B2 * C + c - s2]);
-    else
-        return 0.25 * (F3[B1 * C + c] + F3[B1 * C + c - s1] - F1[B3 * C + c] - F1[B3 * C + c - s3]);
-}
-
-// ------------------------------------------------------------------ stage rhs
-
-// Generalized-minmod slope of the derived quantities used by the EMHD
-// sources: Theta, u_0..u_3, u^1..u^3 (8 values).
-template <int NV, class G>
-__device__ __forceinline__ void emhd_point(const double* P, const G& g, const Phys& ph, double* X)
-{
-    St<NV> s;
-    derive<NV>(P, g, ph, s);
-    X[0] = s.pg / P[RHO];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) X[1 + m] = s.ucov[m];
-#pragma unroll
-    for (int m = 1; m < 4; ++m) X[4 + m] = s.ucon[m];
-}
-
-template <int NV>
-__device__ __forceinline__ void load_cell(const double* P, long cells, long m, double* out)
-{
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = P[(long)v * cells + m];
-}
-
-// One thread per interior zone:
-//   rhs_v = U_v(P_n)/dt' - divF_v(P^E) + S^E_v(P^E)
-// plus, for EMHD, every P-independent part of the relaxation sources folded
-// into rhs_q, rhs_DP, and the coefficients the Newton residual needs.
+// One thread per interior zone: the stage right-hand side (zone_rhs), stored
+// for the Newton kernel.
 template <int NV, class G, int ND>
 __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
 {
     const long z = (long)blockIdx.x * kBlock + threadIdx.x;
-    const Layout& L = a.L;
-    if (z >= L.nz) return;
-    const int ii = (int)(z % L.n[0]);
-    const int jj = (int)((z / L.n[0]) % L.n[1]);
-    const int kk = (int)(z / ((long)L.n[0] * L.n[1]));
-    const int i = ii + L.g[0], j = jj + L.g[1], k = kk + L.g[2];
-    const long m = L.cell(i, j, k);
-    const long C = L.cells;
-    constexpr int nd = ND;
-
-    // divergence of the face fluxes, B rows from the flux-CT EMFs
-    double divF[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int d = 0; d < nd; ++d) {
-            const long st = L.stride(d);
-            double fr, fl;
-            const bool ct = nd >= 2 && v >= B1 && v <= B3 && (nd == 3 || v != B3);
-            if (!ct) {
-                fr = a.F[d][(long)v * C + m + st];
-                fl = a.F[d][(long)v * C + m];
-            } else {
-                const int b = v - B1;
-                const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
-                // face B^b flux through faces normal to d, from the edge EMFs
-                auto face = [&](long c) -> double {
-                    if (b == d) return 0.0;
-                    if (d == 0 && b == 1) return 0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s2));
-                    if (d == 0 && b == 2) return -0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s3));
-                    if (d == 1 && b == 0) return -0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s1));
-                    if (d == 1 && b == 2) return 0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s3));
-                    if (d == 2 && b == 0) return 0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s1));
-                    return -0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s2));  // d == 2 && b == 1
-                };
-                fr = face(m + st);
-                fl = face(m);
-            }
-            s += (fr - fl) / L.dx[d];
-        }
-        divF[v] = s;
-    }
-
+    if (z >= a.L.nz) return;
+    double rhs[NV], co[kEmhdCoef];
     G g;
-    if constexpr (!G::kFlat) load_geo(g, a.geo.centre, (size_t)((long)j * L.N[0] + i), a.geo.stride);
-    const double idt = 1.0 / a.dtp;
-    double Pn[NV], PE[NV];
-    load_cell<NV>(a.Pn, C, m, Pn);
-    load_cell<NV>(a.PE, C, m, PE);
-    St<NV> sn, sE;
-    derive<NV>(Pn, g, a.ph, sn);
-    derive<NV>(PE, g, a.ph, sE);
-    double Un[NV];
-    conserved<NV>(Pn, g, sn, a.ph, Un);
-
-    // explicit geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E
-    double src[NV];
+    zone_rhs<NV, G, ND, true>(a, z, rhs, co, g);
+    const long nz = a.L.nz;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) src[v] = 0.0;
-    double conn[4][4][4];
-    if constexpr (!G::kFlat) {
-        const size_t p = (size_t)((long)j * L.N[0] + i);
-#pragma unroll
-        for (int l = 0; l < 4; ++l)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) conn[l][q / 4][q % 4] = a.geo.conn[(size_t)(l * 16 + q) * a.geo.stride + p];
-        double T[4][4];
-        trow<NV, 0>(PE, sE, T[0]);
-        trow<NV, 1>(PE, sE, T[1]);
-        trow<NV, 2>(PE, sE, T[2]);
-        trow<NV, 3>(PE, sE, T[3]);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            double s = 0.0;
-#pragma unroll
-            for (int kap = 0; kap < 4; ++kap)
-#pragma unroll
-                for (int lam = 0; lam < 4; ++lam) s += T[kap][lam] * conn[lam][n][kap];
-            src[UU + n] = g.gdet() * s;
-        }
-    }
-
-    double rhs[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) rhs[v] = Un[v] * idt - divF[v] + src[v];
-
-    double sq = 0.0, sdiv = 0.0, sdp = 0.0;
+    for (int v = 0; v < NV; ++v) a.rhs[(long)v * nz + z] = rhs[v];
     if constexpr (NV == 10) {
-        // limited slopes of Theta, u_mu, u^i of P^E (Sec. 2.3)
-        double X0[8];
-        emhd_point<NV>(PE, g, a.ph, X0);
-        double dX[3][8];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) dX[d][q] = 0.0;
-#pragma unroll
-        for (int d = 0; d < nd; ++d) {
-            const long st = L.stride(d);
-            double Pm[NV], Pp[NV], Xm[8], Xp[8];
-            load_cell<NV>(a.PE, C, m - st, Pm);
-            load_cell<NV>(a.PE, C, m + st, Pp);
-            G gm, gp;
-            if constexpr (!G::kFlat) {
-                const int im = d == 0 ? i - 1 : i, jm = d == 1 ? j - 1 : j;
-                const int ip = d == 0 ? i + 1 : i, jp = d == 1 ? j + 1 : j;
-                load_geo(gm, a.geo.centre, (size_t)((long)jm * L.N[0] + im), a.geo.stride);
-                load_geo(gp, a.geo.centre, (size_t)((long)jp * L.N[0] + ip), a.geo.stride);
-            }
-            emhd_point<NV>(Pm, gm, a.ph, Xm);
-            emhd_point<NV>(Pp, gp, a.ph, Xp);
-            const double idx = 1.0 / L.dx[d];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) dX[d][q] = gmm(X0[q] - Xm[q], Xp[q] - X0[q], a.ph.theta) * idx;
-        }
-        const double theta = X0[0];
-        double a1 = 0.0, a2 = 0.0, b1 = 0.0, divs = 0.0;
-#pragma unroll
-        for (int d = 0; d < nd; ++d) {
-            a1 += sE.bh[d + 1] * dX[d][0];
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                a2 += sE.bh[mu] * sE.ucon[d + 1] * dX[d][1 + mu];
-                b1 += sE.bh[d + 1] * sE.bh[mu] * dX[d][1 + mu];
-            }
-            divs += dX[d][4 + d + 1];
-        }
-        double ga = 0.0, gb = 0.0, gdv = 0.0;
-        if constexpr (!G::kFlat) {
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int n = 0; n < 4; ++n)
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        ga += sE.bh[mu] * conn[l][n][mu] * sE.ucon[n] * sE.ucov[l];
-                        gb += sE.bh[mu] * sE.bh[n] * conn[l][mu][n] * sE.ucov[l];
-                    }
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int l = 0; l < 4; ++l) gdv += conn[mu][mu][l] * sE.ucon[l];
-        }
-        sq = a1 + theta * (a2 - ga);
-        sdiv = divs + gdv;
-        sdp = b1 - gb;
-
-        // fold the P-independent parts of the relaxation sources
-        const Phys& ph = a.ph;
-        const double gd = g.gdet();
-        const double tau = ph.tau;
-        const double rhoE = PE[RHO], thE = sE.pg / PE[RHO], u0E = sE.ucon[0];
-        double qtE, dptE, qtn, dptn;
-        rescaled<NV>(PE, sE, ph, qtE, dptE);
-        rescaled<NV>(Pn, sn, ph, qtn, dptn);
-        const double kqE = sqrt(tau / (ph.chi * rhoE * thE * thE));
-        const double kdE = sqrt(tau / (ph.nu * rhoE * thE));
-        const double cq = (kqE / tau) * (-rhoE * ph.chi);
-        const double cd = (kdE / tau) * (3.0 * rhoE * ph.nu);
-        const double thn = sn.pg / Pn[RHO];
-        const double u0n = sn.ucon[0];
-        const double cbun = sE.bh[0] * sn.ucov[0] + sE.bh[1] * sn.ucov[1] + sE.bh[2] * sn.ucov[2] + sE.bh[3] * sn.ucov[3];
-        rhs[QQ] += gd * (-qtn / (2.0 * tau) + cq * sq + 0.5 * qtE * sdiv);
-        rhs[DP] += gd * (-dptn / (2.0 * tau) + cd * (sdp - sdiv / 3.0) + 0.5 * dptE * sdiv);
-        double* co = a.coef;
-        const long nz = L.nz;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) co[mu * nz + z] = sE.bh[mu];
-        co[4 * nz + z] = thn;
-        co[5 * nz + z] = u0n;
-        co[6 * nz + z] = cbun;
-        co[7 * nz + z] = gd * cq * sE.bh[0] * idt;
-        co[8 * nz + z] = gd * cq * thE * u0E * idt;
-        co[9 * nz + z] = gd * 0.5 * qtE * idt;
-        co[10 * nz + z] = gd * cd * sE.bh[0] * idt;
-        co[11 * nz + z] = gd * (-(kdE / tau) * rhoE * ph.nu + 0.5 * dptE) * idt;
-        co[12 * nz + z] = gd / (2.0 * tau);
-    }
-
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.rhs[(long)v * L.nz + z] = rhs[v];
-    if (a.mlp_x) {
-        // learned-guess features (dimensionless): the change of U the stage
-        // asks for, relative to U_rho(P_n); the P_n state; lapse and g^{01},
-        // g^{11} (constant in Minkowski)
-        float x[kMlpIn];
-#pragma unroll
-        for (int q = 0; q < kMlpIn; ++q) x[q] = 0.0f;
-        const double ur = Un[RHO];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) x[v] = (float)((rhs[v] * a.dtp - Un[v]) / ur);
-        x[NV] = (float)(Pn[UU] / Pn[RHO]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[NV + 1 + i] = (float)Pn[U1 + i];
-        const double isr = 1.0 / sqrt(Pn[RHO]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[NV + 4 + i] = (float)(Pn[B1 + i] * isr);
-        if constexpr (NV == 10) {
-            x[NV + 7] = (float)(Pn[QQ] / Pn[UU]);
-            x[NV + 8] = (float)(Pn[DP] / Pn[UU]);
-        }
-        x[kMlpIn - 3] = (float)g.alpha();
-        x[kMlpIn - 2] = G::nzn(0, 1) ? (float)g.gcon(0, 1) : 0.0f;
-        x[kMlpIn - 1] = (float)g.gcon(1, 1);
-        float* xo = a.mlp_x + z * kMlpIn;
-#pragma unroll
-        for (int q = 0; q < kMlpIn; ++q) xo[q] = x[q];
-    }
-    if (a.dbg_divF) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            a.dbg_divF[(long)v * L.nz + z] = divF[v];
-            a.dbg_src[(long)v * L.nz + z] = src[v];
-        }
-        if (a.dbg_sp) {
-            a.dbg_sp[3 * z + 0] = sq;
-            a.dbg_sp[3 * z + 1] = sdiv;
-            a.dbg_sp[3 * z + 2] = sdp;
-        }
+        for (int q = 0; q < kEmhdCoef; ++q) a.coef[(long)q * nz + z] = co[q];
     }
 }
 

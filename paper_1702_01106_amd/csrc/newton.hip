@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "grim_internal.h"
+#include "grim_rhs.h"
 #include "grim_zone.h"
 
 namespace grim {
@@ -228,10 +229,12 @@ struct ZoneSolve {
     uint8_t fl;
 };
 
-// Start zone z: load its constants, P_n (or the caller's guess) with B at its
-// explicit update (the exact root of the B rows), the learned candidate if one
-// is given and its residual is smaller, and the initial residual.
-template <int NV, class G>
+// Start zone z: its constants (read from the rhs kernel's output, or for
+// ND > 0 computed here from the face fluxes), P_n (or the caller's guess) with
+// B at its explicit update (the exact root of the B rows), the learned
+// candidate if one is given and its residual is smaller, and the initial
+// residual.
+template <int NV, class G, int ND>
 __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const double* guess, const float* mlp_y,
                                          ZoneSolve<NV, G>& s)
 {
@@ -239,7 +242,13 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
     const Phys& ph = a.s.ph;
     s.z = z;
     s.cell = zone_cell(L, z);
-    load_zone<NV, G>(a.s, z, s.cell, s.zc);
+    if constexpr (ND == 0) {
+        load_zone<NV, G>(a.s, z, s.cell, s.zc);
+    } else {
+        double co[kEmhdCoef];
+        zone_rhs<NV, G, ND, false>(a.s, z, s.zc.rhs, co, s.zc.g);
+        zone_from_rhs<NV, G>(a.s, co, s.zc);
+    }
     s.fB = a.s.dtp / s.zc.g.gdet();
     s.k = 0;
     s.iters = 0;
@@ -458,11 +467,12 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
     }
 }
 
-// A zone per lane: the wave runs until its slowest zone has finished.  (A
+// A zone per lane: the wave runs until its slowest zone has finished.  ND > 0:
+// fused with the stage right-hand side of an ND-dimensional grid.  (A
 // work-queue variant, where a lane that finished took the next zone of its
 // wave's range, ran 20-45% slower on every workload measured and was
 // dropped.)
-template <int NV, class G, typename JT>
+template <int NV, class G, typename JT, int ND>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
     const long z = (long)blockIdx.x * kWave + threadIdx.x;
@@ -475,7 +485,7 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     LaneStats ls;
     if (active) {
         ZoneSolve<NV, G> s;
-        zs_begin<NV, G>(a, z, retry ? nullptr : a.guess, retry ? nullptr : a.mlp_y, s);
+        zs_begin<NV, G, ND>(a, z, retry ? nullptr : a.guess, retry ? nullptr : a.mlp_y, s);
         while (!zs_step<NV, G, JT>(a, s)) {
         }
         zs_finish<NV, G>(a, s, retry, ls);
@@ -483,8 +493,8 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     if (a.stats) flush_stats(a, ls);
 }
 
-template <int NV, class G>
-hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
+template <int NV, class G, int ND>
+hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
     NewtonArgs b = a;
@@ -492,16 +502,34 @@ hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
         // FP32 pass, then the FP64 retry of the zones it marks (needs flags)
         if (!a.flags) return hipErrorInvalidValue;
         b.pass = 1;
-        hipLaunchKernelGGL((k_newton<NV, G, float>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, float, ND>), grid, blk, 0, st, b);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         b.pass = 2;
-        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, double, ND>), grid, blk, 0, st, b);
     } else {
         b.pass = 0;
-        hipLaunchKernelGGL((k_newton<NV, G, double>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, double, ND>), grid, blk, 0, st, b);
     }
     return hipGetLastError();
+}
+
+// The fused form exists for Minkowski only: with the Kerr tables (16 metric
+// and 64 connection values per zone) the fused kernel needs more registers
+// than the Newton solve alone and loses occupancy or spills.
+template <int NV, class G>
+hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
+{
+    if constexpr (G::kFlat) {
+        if (a.fused) {
+            switch (a.s.L.ndim) {
+                case 1: return newton_nd<NV, G, 1>(a, jac_f32, st);
+                case 2: return newton_nd<NV, G, 2>(a, jac_f32, st);
+                default: return newton_nd<NV, G, 3>(a, jac_f32, st);
+            }
+        }
+    }
+    return newton_nd<NV, G, 0>(a, jac_f32, st);
 }
 
 }  // namespace
