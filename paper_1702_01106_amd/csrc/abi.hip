@@ -29,6 +29,7 @@ struct grim_ctx {
     bool own_st = false;
     hipStream_t cap = nullptr;      // private stream used only for graph capture
     double* P[2] = {nullptr, nullptr};  // ghosted state buffers (ping-pong)
+    double* H = nullptr;                // ghosted half-step state P_{n+1/2}
     int cur = 0;                         // buffer holding the current state
     double* F[3] = {nullptr, nullptr, nullptr};
     double* E[3] = {nullptr, nullptr, nullptr};
@@ -116,7 +117,7 @@ void release(grim_ctx* c)
         if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->own_st && c->st) hipStreamDestroy(c->st);
-    void* ptrs[] = {c->P[0], c->P[1], c->F[0], c->F[1], c->F[2], c->E[0], c->E[1], c->E[2], c->rhs, c->coef,
+    void* ptrs[] = {c->P[0], c->P[1], c->H, c->F[0], c->F[1], c->F[2], c->E[0], c->E[1], c->E[2], c->rhs, c->coef,
                     c->interior, c->hookP[0], c->hookP[1], c->iters, c->resid, c->flags, c->stats, c->u64,
                     c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn, c->mlp_p,
                     c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->mlp_x, c->mlp_y, c->mlp_grad, c->adam_m, c->adam_v,
@@ -275,18 +276,20 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     return GRIM_OK;
 }
 
-// One full step from buffer `from` into the other buffer, enqueued on st.
-// The state buffers always hold valid ghosts: grim_set_prims fills them, and
-// each stage's Newton kernel writes the ghost images of every zone it solves.
+// One full step from buffer `from` into the other buffer, enqueued on st:
+// stage 1 from P_n into H (P_{n+1/2}), stage 2 with P^E = H into the other
+// buffer.  No stage writes a buffer it reads: the Newton kernel reads P^E
+// when it computes the right-hand side itself, so writing P_{n+1} over
+// P_{n+1/2} would race with other waves' reads of their neighbours.  The
+// state buffers always hold valid ghosts: grim_set_prims fills them, and each
+// stage's Newton kernel writes the ghost images of every zone it solves.
 int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st, Collect* col = nullptr)
 {
     double* A = c->P[from];
     double* B = c->P[1 - from];
-    int rc = enqueue_stage(c, A, A, 0.5 * dt, B, 0, st, col);
+    int rc = enqueue_stage(c, A, A, 0.5 * dt, c->H, 0, st, col);
     if (rc) return rc;
-    // stage 2 writes P_{n+1} (and its ghosts) over P^E = P_{n+1/2}: the
-    // Newton kernel does not read P^E, which the flux stage has consumed.
-    return enqueue_stage(c, A, B, dt, B, 1, st, col);
+    return enqueue_stage(c, A, c->H, dt, B, 1, st, col);
 }
 
 int ensure_mlp_zone_buffers(grim_ctx* c)
@@ -421,6 +424,7 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     const size_t nv = (size_t)c->nvar;
     int rc = GRIM_OK;
     for (int i = 0; i < 2 && !rc; ++i) rc = dalloc(c, &c->P[i], nv * L.cells);
+    if (!rc) rc = dalloc(c, &c->H, nv * L.cells);
     for (int d = 0; d < cfg->ndim && !rc; ++d) rc = dalloc(c, &c->F[d], nv * L.cells);
     if (cfg->ndim >= 2)
         for (int d = 0; d < 3 && !rc; ++d)
@@ -452,6 +456,7 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     }
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMemsetAsync(c->P[i], 0, sizeof(double) * nv * L.cells, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->H, 0, sizeof(double) * nv * L.cells, c->st);
     for (int d = 0; d < 3 && e == hipSuccess; ++d) {
         if (c->F[d]) e = hipMemsetAsync(c->F[d], 0, sizeof(double) * nv * L.cells, c->st);
         if (e == hipSuccess && c->E[d]) e = hipMemsetAsync(c->E[d], 0, sizeof(double) * L.cells, c->st);

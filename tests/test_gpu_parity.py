@@ -289,6 +289,47 @@ def test_failure_flags_match_oracle(torch_cuda, oracle_mod):
     assert np.array_equal(gfl.ravel() & 16, ofl & 16)
 
 
+@pytest.mark.timeout(300)
+def test_fused_and_stored_rhs_agree_at_scale(torch_cuda, oracle_mod):
+    """512^2 EMHD, four waves per SIMD, so waves of one launch run at
+    different times: the Newton kernel that computes each zone's right-hand
+    side itself (the plain path) and the one that reads it from the rhs kernel
+    (taken here with a network guess that is rejected in every zone) agree bit
+    for bit over three steps, and the third step matches the oracle."""
+    from oracle import mlp_oracle as M
+    from paper_1702_01106_amd import grim
+
+    wl = W.workload("emhd2d_modes_512")
+    P0 = W.initial_state(wl, seed=0)
+    plain = _ctx(wl)
+    plain.set_prims(P0)
+    dt = plain.cfl_dt(wl["cfl"])
+    _say("512^2: two plain steps")
+    plain.run(dt, 2, use_graph=True)
+    P2 = plain.get_prims()
+    st = plain.run(dt, 1, use_graph=True)
+    P3 = plain.get_prims()
+    assert st["n_fail"] == 0
+    junk = _ctx(dict(wl, guess="mlp"))
+    w = (M.init_params(9) * 1e3).astype(np.float32)
+    w[M.N_PARAMS - 80:] = 1.0
+    grim.grim_mlp_set_weights(junk.ctx, w)
+    junk.set_prims(P0)
+    _say("512^2: three steps through the stored right-hand side")
+    sj = junk.run(dt, 3, use_graph=True)
+    assert sj["n_fallback"] == sj["zone_stages"]
+    assert np.array_equal(junk.get_prims(), P3)
+    _say("512^2: one oracle step (twice, for its spread)")
+    o = oracle_mod.Oracle(wl)
+    ref, _ = o.step(P2, dt, 1)
+    # q and DP start at zero, so their family scale is tiny and a stop of
+    # Newton anywhere below the tolerance shows as ~1e-6 of it: bound by the
+    # oracle's own answer under a 1e-12 relative change of its input
+    spread, _ = _oracle_spread(lambda Q: (o.step(Q, dt, 1)[0], None), P2, rel=1e-12, base=(ref, None))
+    _say(f"  oracle spread {np.array2string(spread, precision=1)}")
+    _within_spread(prim_rel_err(P3, ref), spread, 1e-8)
+
+
 def test_f64_retry_of_failed_f32_zones(torch_cuda):
     """Forced from the host: with k_max = 1 and tol = 1e-14 every FP32 solve
     fails, so every zone is solved again from P_n with the FP64 Jacobian; the
