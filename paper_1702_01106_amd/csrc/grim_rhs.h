@@ -118,31 +118,47 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
     double Un[NV];
     conserved<NV>(Pn, g, sn, a.ph, Un);
 
-    // explicit geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E
+    // explicit geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E, and for
+    // EMHD the connection parts of the q0, DP0 and div u terms at P^E:
+    //   ga = bhat^mu Gamma^l_{n mu} u^n u_l,  gb = bhat^mu bhat^n Gamma^l_{mu n} u_l,
+    //   gdv = Gamma^mu_{mu l} u^l.
+    // Gamma is read one upper index l at a time (16 values), so at most 16 of
+    // its 64 entries are live in registers.
     double src[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) src[v] = 0.0;
-    double conn[4][4][4];
+    double ga = 0.0, gb = 0.0, gdv = 0.0;
     if constexpr (!G::kFlat) {
         const size_t p = (size_t)((long)j * L.N[0] + i);
-#pragma unroll
-        for (int l = 0; l < 4; ++l)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) conn[l][q / 4][q % 4] = a.geo.conn[(size_t)(l * 16 + q) * a.geo.stride + p];
         double T[4][4];
         trow<NV, 0>(PE, sE, T[0]);
         trow<NV, 1>(PE, sE, T[1]);
         trow<NV, 2>(PE, sE, T[2]);
         trow<NV, 3>(PE, sE, T[3]);
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            double s = 0.0;
+        for (int l = 0; l < 4; ++l) {
+            double c[4][4];  // Gamma^l_{a b}
 #pragma unroll
-            for (int kap = 0; kap < 4; ++kap)
+            for (int q = 0; q < 16; ++q) c[q / 4][q % 4] = a.geo.conn[(size_t)(l * 16 + q) * a.geo.stride + p];
 #pragma unroll
-                for (int lam = 0; lam < 4; ++lam) s += T[kap][lam] * conn[lam][n][kap];
-            src[UU + n] = g.gdet() * s;
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int kap = 0; kap < 4; ++kap) s4[n] += T[kap][l] * c[n][kap];
+            if constexpr (NV == 10) {
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        ga += sE.bh[mu] * c[n][mu] * sE.ucon[n] * sE.ucov[l];
+                        gb += sE.bh[mu] * sE.bh[n] * c[mu][n] * sE.ucov[l];
+                    }
+#pragma unroll
+                for (int n = 0; n < 4; ++n) gdv += c[l][n] * sE.ucon[n];
+            }
         }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) src[UU + n] = g.gdet() * s4[n];
     }
 
 #pragma unroll
@@ -150,16 +166,16 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
 
     double sq = 0.0, sdiv = 0.0, sdp = 0.0;
     if constexpr (NV == 10) {
-        // limited slopes of Theta, u_mu, u^i of P^E (Sec. 2.3)
+        // limited slopes of Theta, u_mu, u^i of P^E (Sec. 2.3), folded into
+        // the sums a1 = bhat^d dTheta/dx^d, a2 = bhat^mu u^d du_mu/dx^d,
+        // b1 = bhat^d bhat^mu du_mu/dx^d and divs = du^d/dx^d one direction
+        // at a time
         double X0[8];
         emhd_point<NV>(PE, g, a.ph, X0);
-        double dX[3][8];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) dX[d][q] = 0.0;
+        double a1 = 0.0, a2 = 0.0, b1 = 0.0, divs = 0.0;
 #pragma unroll
         for (int d = 0; d < nd; ++d) {
+            const double bhd = sE.bh[d + 1], ud = sE.ucon[d + 1];
             const long st = L.stride(d);
             double Pm[NV], Pp[NV], Xm[8], Xp[8];
             load_cell<NV>(a.PE, C, m - st, Pm);
@@ -174,37 +190,18 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
             emhd_point<NV>(Pm, gm, a.ph, Xm);
             emhd_point<NV>(Pp, gp, a.ph, Xp);
             const double idx = 1.0 / L.dx[d];
+            double dX[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) dX[d][q] = gmm(X0[q] - Xm[q], Xp[q] - X0[q], a.ph.theta) * idx;
-        }
-        const double theta = X0[0];
-        double a1 = 0.0, a2 = 0.0, b1 = 0.0, divs = 0.0;
-#pragma unroll
-        for (int d = 0; d < nd; ++d) {
-            a1 += sE.bh[d + 1] * dX[d][0];
+            for (int q = 0; q < 8; ++q) dX[q] = gmm(X0[q] - Xm[q], Xp[q] - X0[q], a.ph.theta) * idx;
+            a1 += bhd * dX[0];
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
-                a2 += sE.bh[mu] * sE.ucon[d + 1] * dX[d][1 + mu];
-                b1 += sE.bh[d + 1] * sE.bh[mu] * dX[d][1 + mu];
+                a2 += sE.bh[mu] * ud * dX[1 + mu];
+                b1 += bhd * sE.bh[mu] * dX[1 + mu];
             }
-            divs += dX[d][4 + d + 1];
+            divs += dX[4 + d + 1];
         }
-        double ga = 0.0, gb = 0.0, gdv = 0.0;
-        if constexpr (!G::kFlat) {
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int n = 0; n < 4; ++n)
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        ga += sE.bh[mu] * conn[l][n][mu] * sE.ucon[n] * sE.ucov[l];
-                        gb += sE.bh[mu] * sE.bh[n] * conn[l][mu][n] * sE.ucov[l];
-                    }
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int l = 0; l < 4; ++l) gdv += conn[mu][mu][l] * sE.ucon[l];
-        }
+        const double theta = X0[0];
         sq = a1 + theta * (a2 - ga);
         sdiv = divs + gdv;
         sdp = b1 - gb;
