@@ -25,6 +25,19 @@ struct Layout {
     __host__ __device__ long stride(int d) const { return d == 0 ? 1L : (d == 1 ? (long)N[0] : (long)N[0] * N[1]); }
 };
 
+// Interior zone index z -> interior coordinates (i, j, k).  The host limits
+// a grid to 2e9 zones, so 32-bit unsigned division is exact (a 64-bit one
+// is several times longer).
+__device__ __forceinline__ void zone_ijk(const Layout& L, long z, int& i, int& j, int& k)
+{
+    const unsigned u = (unsigned)z, n0 = (unsigned)L.n[0], n1 = (unsigned)L.n[1];
+    const unsigned r = u / n0;
+    const unsigned kk = r / n1;
+    i = (int)(u - r * n0);
+    j = (int)(r - kk * n1);
+    k = (int)kk;
+}
+
 // Device-side accumulators of the solver statistics.  kStatCopies copies,
 // one 128-byte line each: a wave adds into copy (block index mod copies), so
 // no address sees more than 1/kStatCopies of the waves' atomics (atomics to

@@ -65,9 +65,8 @@ template <int NV, class G, int ND, bool kOut>
 __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs, double* co, G& g)
 {
     const Layout& L = a.L;
-    const int ii = (int)(z % L.n[0]);
-    const int jj = (int)((z / L.n[0]) % L.n[1]);
-    const int kk = (int)(z / ((long)L.n[0] * L.n[1]));
+    int ii, jj, kk;
+    zone_ijk(L, z, ii, jj, kk);
     const int i = ii + L.g[0], j = jj + L.g[1], k = kk + L.g[2];
     const long m = L.cell(i, j, k);
     const long C = L.cells;

@@ -30,10 +30,8 @@ struct ZoneC {
 // Interior zone index z -> ghosted cell index.
 __device__ __forceinline__ long zone_cell(const Layout& L, long z)
 {
-    const int i = (int)(z % L.n[0]);
-    const long r = z / L.n[0];
-    const int j = (int)(r % L.n[1]);
-    const int k = (int)(r / L.n[1]);
+    int i, j, k;
+    zone_ijk(L, z, i, j, k);
     return L.cell(i + L.g[0], j + L.g[1], k + L.g[2]);
 }
 

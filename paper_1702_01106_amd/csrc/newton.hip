@@ -79,7 +79,7 @@ __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
     return ok;
 }
 
-__device__ __forceinline__ double wave_sum(double x)
+__device__ __forceinline__ unsigned long long wave_sumu64(unsigned long long x)
 {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
@@ -162,59 +162,68 @@ __device__ __forceinline__ bool newton_dir(const double* P, const double* R, con
 }
 
 // Ghosted coordinates along one direction that take their value from
-// interior index p (p itself first): the inverses of the ghost maps
-// (periodic wrap, outflow clamp, polar mirror, Ng = 2).  Returns the count;
-// mirror[m] marks a polar image.
-__device__ __forceinline__ int ghost_images(int p, int g, int n, int bc, int* q, bool* mirror)
+// ghosted index p of an interior cell: p itself and up to two ghost images,
+// the inverses of the ghost maps (periodic wrap, outflow clamp, polar mirror)
+// for Ng = 2 and n >= 2, which the host enforces.  Held in registers (an
+// array indexed by a per-lane count would be placed in LDS or scratch).
+struct GhostSlots {
+    int cnt;     // 1 + number of images
+    int q1, q2;  // the images (q2 only when cnt == 3)
+};
+
+__device__ __forceinline__ GhostSlots ghost_slots(int p, int g, int n, int bc)
 {
-    int c = 0;
-    q[c] = p;
-    mirror[c++] = false;
+    GhostSlots s;
     if (bc == 0) {
-        if (p >= n) { q[c] = p - n; mirror[c++] = false; }          // lower ghost p - n in [0, g)
-        if (p < 2 * g) { q[c] = p + n; mirror[c++] = false; }       // upper ghost in [g + n, 2g + n)
+        // periodic: lower ghost p - n (p >= n), upper ghost p + n (p < 2g)
+        const bool lo = p >= n, hi = p < 2 * g;
+        s.cnt = 1 + (int)lo + (int)hi;
+        s.q1 = lo ? p - n : p + n;
+        s.q2 = p + n;
     } else if (bc == 1) {
-        if (p == g)
-            for (int m = 0; m < g; ++m) { q[c] = m; mirror[c++] = false; }
-        if (p == g + n - 1)
-            for (int m = 0; m < g; ++m) { q[c] = g + n + m; mirror[c++] = false; }
+        // outflow: the first interior cell fills both lower ghosts, the last both upper
+        const bool lo = p == g, hi = p == g + n - 1;
+        s.cnt = (lo || hi) ? 3 : 1;
+        s.q1 = lo ? 0 : g + n;
+        s.q2 = s.q1 + 1;
     } else {
-        if (p < 2 * g) { q[c] = 2 * g - 1 - p; mirror[c++] = true; }
-        if (p >= n) { q[c] = 2 * (g + n) - 1 - p; mirror[c++] = true; }
+        // polar mirror about each face: 2g - 1 - p (p < 2g), 2(g + n) - 1 - p (p >= n)
+        const bool lo = p < 2 * g, hi = p >= n;
+        s.cnt = 1 + (int)lo + (int)hi;
+        s.q1 = lo ? 2 * g - 1 - p : 2 * (g + n) - 1 - p;
+        s.q2 = 2 * (g + n) - 1 - p;
     }
-    return c;
+    return s;
 }
+
+__device__ __forceinline__ int slot(int a, int p, const GhostSlots& s) { return a == 0 ? p : (a == 1 ? s.q1 : s.q2); }
 
 // Store a zone's primitives at its cell and at every ghost cell that maps to
 // it (the composite map is the product of the per-direction maps; a polar
-// image in X2 negates utilde^2 and B^2).
+// image in X2 negates utilde^2 and B^2).  (i, j, k) are interior coordinates.
 template <int NV>
-__device__ __forceinline__ void store_with_ghosts(const Layout& L, const int* bc, long z, const double* P, double* out)
+__device__ __forceinline__ void store_with_ghosts(const Layout& L, const int* bc, int i, int j, int k, const double* P,
+                                                  double* out)
 {
-    const int p[3] = {(int)(z % L.n[0]) + L.g[0], (int)((z / L.n[0]) % L.n[1]) + L.g[1],
-                      (int)(z / ((long)L.n[0] * L.n[1])) + L.g[2]};
-    int q[3][5];
-    bool mir[3][5];
-    int cnt[3];
+    const int p0 = i + L.g[0], p1 = j + L.g[1], p2 = k + L.g[2];
+    const GhostSlots s0 = ghost_slots(p0, L.g[0], L.n[0], bc[0]);
+    GhostSlots s1{1, 0, 0}, s2{1, 0, 0};
+    if (L.ndim > 1) s1 = ghost_slots(p1, L.g[1], L.n[1], bc[1]);
+    if (L.ndim > 2) s2 = ghost_slots(p2, L.g[2], L.n[2], bc[2]);
+    const bool polar = bc[1] == 2;
+    const long C = L.cells;
+    for (int a2 = 0; a2 < s2.cnt; ++a2) {
+        const int q2 = slot(a2, p2, s2);
+        for (int a1 = 0; a1 < s1.cnt; ++a1) {
+            const int q1 = slot(a1, p1, s1);
+            const bool flip = polar && a1 > 0;
+            for (int a0 = 0; a0 < s0.cnt; ++a0) {
+                double* o = out + L.cell(slot(a0, p0, s0), q1, q2);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d < L.ndim) {
-            cnt[d] = ghost_images(p[d], L.g[d], L.n[d], bc[d], q[d], mir[d]);
-        } else {
-            cnt[d] = 1;
-            q[d][0] = p[d];
-            mir[d][0] = false;
+                for (int v = 0; v < NV; ++v) o[(long)v * C] = (flip && (v == U2 || v == B2)) ? -P[v] : P[v];
+            }
         }
     }
-    for (int c2 = 0; c2 < cnt[2]; ++c2)
-        for (int c1 = 0; c1 < cnt[1]; ++c1)
-            for (int c0 = 0; c0 < cnt[0]; ++c0) {
-                const long cell = L.cell(q[0][c0], q[1][c1], q[2][c2]);
-                const bool flip = mir[1][c1];
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    out[(long)v * L.cells + cell] = (flip && (v == U2 || v == B2)) ? -P[v] : P[v];
-            }
 }
 
 // Per-lane state of one zone's solve.
@@ -393,9 +402,9 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
 
 // Per-lane accumulators of the statistics over the zones a lane finishes.
 struct LaneStats {
-    double iters = 0, nf = 0, nl = 0, nu = 0, na = 0, nc = 0, nfb = 0, nrt = 0;
-    int mit = 0;
-    unsigned long long rb = 0;
+    int iters = 0, nc = 0;  // Newton iterations, residual evaluations
+    bool nf = false, nl = false, nu = false, na = false, nfb = false, nrt = false;
+    unsigned long long rb = 0;  // bits of the final residual (ordered like the value)
 };
 
 // Floors, flags, outputs and statistics of a finished zone.
@@ -407,14 +416,16 @@ __device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>&
     if (!(s.P[RHO] > 0.0) || !(s.P[UU] > 0.0)) s.fl |= 8;
     if ((a.pass == 1 && (s.fl & (1 | 4 | 16))) || retry) s.fl |= kFlagRetry;
     if (a.s.floors) {
-        const int ii = (int)(z % L.n[0]);
+        const int ii = (int)((unsigned)z % (unsigned)L.n[0]);
         const double r1 = exp(L.xs[0] + (ii + 0.5) * L.dx[0]);
         const double rf = a.s.rho_fl * pow(r1, -1.5), uf = a.s.u_fl * pow(r1, -2.5);
         if (!(s.P[RHO] >= rf)) s.P[RHO] = rf;
         if (!(s.P[UU] >= uf)) s.P[UU] = uf;
     }
     if (a.out_ghosted && a.write_ghosts) {
-        store_with_ghosts<NV>(L, a.bc, z, s.P, a.out);
+        int i, j, k;
+        zone_ijk(L, z, i, j, k);
+        store_with_ghosts<NV>(L, a.bc, i, j, k, s.P, a.out);
     } else if (a.out_ghosted) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.out[(long)v * L.cells + s.cell] = s.P[v];
@@ -422,47 +433,56 @@ __device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>&
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.out[(long)v * L.nz + z] = s.P[v];
     }
-    if (a.iters) a.iters[z] = (retry ? a.iters[z] : 0) + s.iters;
+    if (a.iters) {
+        // the retry pass adds to the FP32 pass's count (the read sits in its
+        // own branch so the first pass does not wait for its stores)
+        if (retry)
+            a.iters[z] += s.iters;
+        else
+            a.iters[z] = s.iters;
+    }
     if (a.resid) a.resid[z] = s.r;
     if (a.flags) a.flags[z] = s.fl;
     // a zone marked for the FP64 retry contributes only its work (iterations,
     // residual calls) to the FP32 pass; the retry pass reports its outcome
     const bool final_ = !(a.pass == 1 && (s.fl & kFlagRetry));
-    ls.iters += s.iters;
-    ls.mit = max(ls.mit, s.iters);
-    ls.nc += s.ncalls;
-    ls.nfb += s.fallback;
-    if (!retry) ls.na += 1.0;
-    else ls.nrt += 1.0;
+    ls.iters = s.iters;
+    ls.nc = s.ncalls;
+    ls.nfb = s.fallback != 0;
+    ls.na = !retry;
+    ls.nrt = retry;
     if (final_) {
-        if (s.fl & (1 | 4 | 16)) ls.nf += 1.0;
-        if (s.fl & 2) ls.nl += 1.0;
-        if (s.fl & 8) ls.nu += 1.0;
+        ls.nf = (s.fl & (1 | 4 | 16)) != 0;
+        ls.nl = (s.fl & 2) != 0;
+        ls.nu = (s.fl & 8) != 0;
         const unsigned long long b =
             isfinite(s.r) ? (unsigned long long)__double_as_longlong(s.r) : 0x7FF0000000000000ull;
         ls.rb = b > ls.rb ? b : ls.rb;
     }
 }
 
-// Wave reduction of the lane statistics, one atomic per wave and counter.
+// Wave reduction of the lane statistics, one atomic per wave and counter:
+// the 0/1 counters are popcounts of ballots; the iteration and residual-call
+// counts share one 64-bit sum (each half stays below 2^32).
 __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats& ls)
 {
-    const double sit = wave_sum(ls.iters);
-    const int mit = wave_max(ls.mit);
-    const double nf = wave_sum(ls.nf), nl = wave_sum(ls.nl), nu = wave_sum(ls.nu);
-    const double na = wave_sum(ls.na), nc = wave_sum(ls.nc), nfb = wave_sum(ls.nfb), nrt = wave_sum(ls.nrt);
+    const unsigned long long both = wave_sumu64(((unsigned long long)(unsigned)ls.nc << 32) | (unsigned)ls.iters);
+    const int mit = wave_max(ls.iters);
     const unsigned long long rb = wave_maxu64(ls.rb);
+    const unsigned long long nf = __popcll(__ballot(ls.nf)), nl = __popcll(__ballot(ls.nl)),
+                             nu = __popcll(__ballot(ls.nu)), na = __popcll(__ballot(ls.na)),
+                             nfb = __popcll(__ballot(ls.nfb)), nrt = __popcll(__ballot(ls.nrt));
     DevStats* ds = a.stats + (blockIdx.x & (kStatCopies - 1));
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicAdd(&ds->iters[a.stage], (unsigned long long)sit);
+        atomicAdd(&ds->iters[a.stage], both & 0xFFFFFFFFull);
         atomicMax(&ds->max_iters, (unsigned)mit);
-        if (nf > 0) atomicAdd(&ds->n_fail, (unsigned long long)nf);
-        if (nl > 0) atomicAdd(&ds->n_ls, (unsigned long long)nl);
-        if (nu > 0) atomicAdd(&ds->n_unphys, (unsigned long long)nu);
-        if (na > 0) atomicAdd(&ds->zone_stages, (unsigned long long)na);
-        if (nrt > 0) atomicAdd(&ds->n_retry, (unsigned long long)nrt);
-        atomicAdd(&ds->resid_calls, (unsigned long long)nc);
-        if (nfb > 0) atomicAdd(&ds->n_fallback, (unsigned long long)nfb);
+        if (nf > 0) atomicAdd(&ds->n_fail, nf);
+        if (nl > 0) atomicAdd(&ds->n_ls, nl);
+        if (nu > 0) atomicAdd(&ds->n_unphys, nu);
+        if (na > 0) atomicAdd(&ds->zone_stages, na);
+        if (nrt > 0) atomicAdd(&ds->n_retry, nrt);
+        atomicAdd(&ds->resid_calls, both >> 32);
+        if (nfb > 0) atomicAdd(&ds->n_fallback, nfb);
         atomicMax(&ds->max_resid_bits, rb);
     }
 }
