@@ -25,6 +25,45 @@ __host__ __device__ constexpr int sidx(int m, int n)
     return m <= n ? m * 4 - m * (m - 1) / 2 + n - m : n * 4 - n * (n - 1) / 2 + m - n;
 }
 
+// Reciprocal, inverse square root and square root for the hot loops: the
+// hardware estimate (relative error below 2^-22 in double precision) refined
+// by Newton-Raphson steps, each of which squares the relative error
+// (Newton's iteration for 1/x and 1/sqrt(x); P. Markstein, IBM J. Res. Dev.
+// 34 (1990) 111).  Two steps give about one unit in the last place at half the
+// instructions and a much shorter dependency chain than the correctly rounded
+// sequences.  Where a step is not finite (zero, infinite or NaN argument) the
+// estimate, which is then the IEEE result, is returned.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    const double r0 = __builtin_amdgcn_rcp(x);
+    const double r1 = fma(fma(-x, r0, 1.0), r0, r0);
+    const double r2 = fma(fma(-x, r1, 1.0), r1, r1);
+    return __builtin_isfinite(r2) ? r2 : r0;
+}
+
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    // the single-precision estimate is within 1 ulp already; one step
+    const float r0 = __builtin_amdgcn_rcpf(x);
+    const float r1 = fmaf(fmaf(-x, r0, 1.0f), r0, r0);
+    return __builtin_isfinite(r1) ? r1 : r0;
+}
+
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    // y <- y + (y/2)(1 - x y^2)
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double y1 = fma(0.5 * y0, fma(-x * y0, y0, 1.0), y0);
+    const double y2 = fma(0.5 * y1, fma(-x * y1, y1, 1.0), y1);
+    return __builtin_isfinite(y2) ? y2 : y0;
+}
+
+// sqrt(x) = x / sqrt(x), exact 0 for x = 0 (the clamp turns 0 * inf into
+// 0 * DBL_MAX).  A negative argument gives -inf or NaN rather than exactly
+// NaN; every caller only tests finiteness.  (A select on x == 0 instead of
+// the clamp costs the stage kernels 30-90 registers.)
+__device__ __forceinline__ double sqrt_nr(double x) { return x * fmin(rsq_nr(x), 1.7976931348623157e308); }
+
 // Physical constants shared by every kernel of one context.
 struct Phys {
     double gam;      // adiabatic index
@@ -134,20 +173,24 @@ __device__ __forceinline__ void derive(const double* P, const G& g, const Phys& 
                 q2 = first ? t : q2 + t;
                 first = false;
             }
-    const double gl = sqrt(1.0 + q2);
+    const double gl2 = 1.0 + q2;
+    const double igl = rsq_nr(gl2);  // 1/gamma
+    const double gl = gl2 * igl;
+    double iu0;
     if constexpr (G::kFlat) {
         s.ucon[0] = gl;
+        iu0 = igl;
 #pragma unroll
         for (int i = 1; i < 4; ++i) s.ucon[i] = P[1 + i];
     } else {
-        s.ucon[0] = gl / g.alpha();
+        s.ucon[0] = gl * rcp_nr(g.alpha());
+        iu0 = g.alpha() * igl;
         const double ga = gl * g.alpha();
 #pragma unroll
         for (int i = 1; i < 4; ++i) s.ucon[i] = P[1 + i] - ga * g.gcon(0, i);
     }
     lower(g, s.ucon, s.ucov);
     const double b0 = P[B1] * s.ucov[1] + P[B2] * s.ucov[2] + P[B3] * s.ucov[3];
-    const double iu0 = 1.0 / s.ucon[0];
     s.bcon[0] = b0;
 #pragma unroll
     for (int i = 1; i < 4; ++i) s.bcon[i] = (P[B1 + i - 1] + b0 * s.ucon[i]) * iu0;
@@ -156,7 +199,7 @@ __device__ __forceinline__ void derive(const double* P, const G& g, const Phys& 
     s.pg = ph.gm1 * P[UU];
     if constexpr (NV == 10) {
         const bool has = s.bsq > 1e-30;
-        const double ib = has ? 1.0 / sqrt(s.bsq) : 0.0;
+        const double ib = has ? rsq_nr(s.bsq) : 0.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             s.bh[m] = s.bcon[m] * ib;
@@ -196,9 +239,9 @@ __device__ __forceinline__ void trow(const double* P, const St<NV>& s, double* T
 template <int NV>
 __device__ __forceinline__ void rescaled(const double* P, const St<NV>& s, const Phys& ph, double& qt, double& dpt)
 {
-    const double ip = 1.0 / s.pg;
-    qt = P[QQ] * ph.kq * sqrt(P[RHO]) * ip;
-    dpt = P[DP] * ph.kd * sqrt(ip);
+    const double isp = rsq_nr(s.pg);  // 1/sqrt(P)
+    qt = P[QQ] * ph.kq * sqrt_nr(P[RHO]) * (isp * isp);
+    dpt = P[DP] * ph.kd * isp;
 }
 
 // Conserved vector U (Sec. 4: sqrt(-g) times rho u^0, T^0_nu, B^i, qt u^0, DPt u^0).
@@ -248,10 +291,10 @@ template <int NV>
 __device__ __forceinline__ double vmax2(const double* P, const St<NV>& s, const Phys& ph)
 {
     const double e = P[RHO] + ph.gam * P[UU];
-    const double cs2 = ph.gam * ph.gm1 * P[UU] / e;
-    const double va2 = s.bsq / (e + s.bsq);
+    const double cs2 = ph.gam * ph.gm1 * P[UU] * rcp_nr(e);
+    const double va2 = s.bsq * rcp_nr(e + s.bsq);
     double ct2 = cs2;
-    if constexpr (NV == 10) ct2 = 0.5 * (cs2 + ph.vq2 + sqrt(cs2 * cs2 + ph.vq2 * ph.vq2)) + ph.vd2;
+    if constexpr (NV == 10) ct2 = 0.5 * (cs2 + ph.vq2 + sqrt_nr(cs2 * cs2 + ph.vq2 * ph.vq2)) + ph.vd2;
     return ct2 + va2 - ct2 * va2;
 }
 
@@ -270,7 +313,7 @@ __device__ __forceinline__ double cmax(const double* P, const G& g, const St<NV>
     B *= -2.0;
     const double C = a * ud * ud - v2 * g.gcon(DIR, DIR);
     const double disc = fmax(B * B - 4.0 * A * C, 0.0);
-    return (fabs(B) + sqrt(disc)) / (2.0 * fabs(A));
+    return (fabs(B) + sqrt_nr(disc)) * rcp_nr(2.0 * fabs(A));
 }
 
 // Generalized minmod slope minmod(theta a, (a+b)/2, theta b) (Sec. 2.3, 2.4.1).

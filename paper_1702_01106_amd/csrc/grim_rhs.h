@@ -40,7 +40,7 @@ __device__ __forceinline__ void emhd_point(const double* P, const G& g, const Ph
 {
     St<NV> s;
     derive<NV>(P, g, ph, s);
-    X[0] = s.pg / P[RHO];
+    X[0] = s.pg * rcp_nr(P[RHO]);
 #pragma unroll
     for (int m = 0; m < 4; ++m) X[1 + m] = s.ucov[m];
 #pragma unroll
@@ -101,7 +101,7 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
                 fr = face(m + st);
                 fl = face(m);
             }
-            s += (fr - fl) / L.dx[d];
+            s += (fr - fl) * (1.0 / L.dx[d]);
         }
         divF[v] = s;
     }
@@ -208,20 +208,21 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         // fold the P-independent parts of the relaxation sources
         const Phys& ph = a.ph;
         const double gd = g.gdet();
-        const double tau = ph.tau;
-        const double rhoE = PE[RHO], thE = sE.pg / PE[RHO], u0E = sE.ucon[0];
+        const double tau = ph.tau, itau = 1.0 / tau;
+        const double rhoE = PE[RHO], thE = sE.pg * rcp_nr(PE[RHO]), u0E = sE.ucon[0];
         double qtE, dptE, qtn, dptn;
         rescaled<NV>(PE, sE, ph, qtE, dptE);
         rescaled<NV>(Pn, sn, ph, qtn, dptn);
-        const double kqE = sqrt(tau / (ph.chi * rhoE * thE * thE));
-        const double kdE = sqrt(tau / (ph.nu * rhoE * thE));
-        const double cq = (kqE / tau) * (-rhoE * ph.chi);
-        const double cd = (kdE / tau) * (3.0 * rhoE * ph.nu);
-        const double thn = sn.pg / Pn[RHO];
+        // sqrt(tau/(chi rho Theta^2)) and sqrt(tau/(nu rho Theta)) at P^E
+        const double kqE = ph.kq * rsq_nr(rhoE * thE * thE);
+        const double kdE = ph.kd * rsq_nr(rhoE * thE);
+        const double cq = (kqE * itau) * (-rhoE * ph.chi);
+        const double cd = (kdE * itau) * (3.0 * rhoE * ph.nu);
+        const double thn = sn.pg * rcp_nr(Pn[RHO]);
         const double u0n = sn.ucon[0];
         const double cbun = sE.bh[0] * sn.ucov[0] + sE.bh[1] * sn.ucov[1] + sE.bh[2] * sn.ucov[2] + sE.bh[3] * sn.ucov[3];
-        rhs[QQ] += gd * (-qtn / (2.0 * tau) + cq * sq + 0.5 * qtE * sdiv);
-        rhs[DP] += gd * (-dptn / (2.0 * tau) + cd * (sdp - sdiv / 3.0) + 0.5 * dptE * sdiv);
+        rhs[QQ] += gd * (-qtn * (0.5 * itau) + cq * sq + 0.5 * qtE * sdiv);
+        rhs[DP] += gd * (-dptn * (0.5 * itau) + cd * (sdp - sdiv * (1.0 / 3.0)) + 0.5 * dptE * sdiv);
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) co[mu] = sE.bh[mu];
         co[4] = thn;
@@ -231,8 +232,8 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         co[8] = gd * cq * thE * u0E * idt;
         co[9] = gd * 0.5 * qtE * idt;
         co[10] = gd * cd * sE.bh[0] * idt;
-        co[11] = gd * (-(kdE / tau) * rhoE * ph.nu + 0.5 * dptE) * idt;
-        co[12] = gd / (2.0 * tau);
+        co[11] = gd * (-(kdE * itau) * rhoE * ph.nu + 0.5 * dptE) * idt;
+        co[12] = gd * (0.5 * itau);
     }
     if constexpr (!kOut) return;
     if (a.mlp_x) {

@@ -100,7 +100,7 @@ __device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G
     if constexpr (NV == 10) {
         double qt, dpt;
         rescaled<NV>(P, s, ph, qt, dpt);
-        const double th = s.pg / P[RHO];
+        const double th = s.pg * rcp_nr(P[RHO]);
         const double bu = zc.bh[0] * s.ucov[0] + zc.bh[1] * s.ucov[1] + zc.bh[2] * s.ucov[2] + zc.bh[3] * s.ucov[3];
         const double dbu = bu - zc.cbun;
         const double du0 = s.ucon[0] - zc.u0n;

@@ -34,6 +34,7 @@ template <int N, typename T>
 __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
 {
     bool ok = true;
+    T inv[N];  // reciprocal pivots
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         T best = fabs(A[k][k]);
@@ -60,10 +61,10 @@ __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
             b[k] = s ? ti : tk;
             b[i] = s ? tk : ti;
         }
-        const T inv = T(1) / A[k][k];
+        inv[k] = rcp_nr(A[k][k]);
 #pragma unroll
         for (int i = k + 1; i < N; ++i) {
-            const T f = A[i][k] * inv;
+            const T f = A[i][k] * inv[k];
 #pragma unroll
             for (int j = k + 1; j < N; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
             b[i] = fma(-f, b[k], b[i]);
@@ -74,7 +75,7 @@ __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
         T s = b[i];
 #pragma unroll
         for (int j = i + 1; j < N; ++j) s = fma(-A[i][j], b[j], s);
-        b[i] = s / A[i][i];
+        b[i] = s * inv[i];
     }
     return ok;
 }
@@ -148,7 +149,7 @@ __device__ __forceinline__ bool newton_dir(const double* P, const double* R, con
         Pe[unk(j)] = pe;
         double Re[NV];
         zone_residual<NV, G>(Pe, zc, ph, Re);
-        const double ih = 1.0 / h;
+        const double ih = rcp_nr(h);
 #pragma unroll
         for (int i = 0; i < N; ++i) J[i][j] = (JT)((Re[unk(i)] - R[unk(i)]) * ih);
     }
@@ -282,7 +283,7 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
     for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
     zone_residual<NV, G>(s.P, s.zc, ph, s.R);
     ++s.ncalls;
-    s.r = s.nscale * sqrt(sumsq<NV>(s.R));
+    s.r = s.nscale * sqrt_nr(sumsq<NV>(s.R));
     if (mlp_y) {
         // keep the learned guess only if its residual is smaller
 #pragma unroll
@@ -290,7 +291,7 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
         double Rc[NV];
         zone_residual<NV, G>(P_alt, s.zc, ph, Rc);
         ++s.ncalls;
-        const double rc = s.nscale * sqrt(sumsq<NV>(Rc));
+        const double rc = s.nscale * sqrt_nr(sumsq<NV>(Rc));
         if (rc < s.r) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -342,7 +343,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
                 for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], s.P[v]);
                 zone_residual<NV, G>(Pt, s.zc, ph, Rt);
                 ++s.ncalls;
-                const double rt = s.nscale * sqrt(sumsq<NV>(Rt));
+                const double rt = s.nscale * sqrt_nr(sumsq<NV>(Rt));
                 if (isfinite(rt)) {
                     have = true;
 #pragma unroll
@@ -396,7 +397,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
     for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
     zone_residual<NV, G>(s.P, s.zc, ph, s.R);
     ++s.ncalls;
-    s.r = s.nscale * sqrt(sumsq<NV>(s.R));
+    s.r = s.nscale * sqrt_nr(sumsq<NV>(s.R));
     return false;
 }
 

@@ -115,6 +115,29 @@ def _state(name, wl):
     return P
 
 
+def _flux_scale(o, wl, P, cap=3000):
+    """Per variable, the size of the LLF face fluxes: max of |F^d_v| and
+    c_max^d |U_v| (the dissipative term) from the oracle's point functions over
+    (a sample of) the zones and the active directions, at each zone's centre."""
+    nv, nd = wl["nvar"], wl["ndim"]
+    n = list(wl["n"]) + [1] * (3 - len(wl["n"]))
+    xs = list(wl["x_start"]) + [0.0] * (3 - len(wl["x_start"]))
+    xe = list(wl["x_end"]) + [1.0] * (3 - len(wl["x_end"]))
+    Pz = P.reshape(nv, -1)
+    zs = np.arange(Pz.shape[1])
+    if zs.size > cap:
+        zs = np.random.default_rng(0).choice(zs, cap, replace=False)
+    fmax = np.zeros(nv)
+    for z in zs:
+        c = (z % n[0], (z // n[0]) % n[1], z // (n[0] * n[1]))
+        X = np.array([0.0] + [xs[d] + (c[d] + 0.5) * (xe[d] - xs[d]) / n[d] for d in range(3)])
+        U = np.abs(o.flux(Pz[:, z], X, 0))
+        for d in range(1, nd + 1):
+            lp, lm = o.speeds(Pz[:, z], X, d)
+            fmax = np.maximum(fmax, np.maximum(np.abs(o.flux(Pz[:, z], X, d)), max(abs(lp), abs(lm)) * U))
+    return fmax
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_explicit_stage(torch_cuda, oracle_mod, name):
     wl, _ = CASES[name]()
@@ -132,9 +155,15 @@ def test_explicit_stage(torch_cuda, oracle_mod, name):
     _say("  max rel err divF %.1e src %.1e" % (
         max(np.abs(gdF[v] - dF[v]).max() / max(np.abs(dF[v]).max(), 1e-300) for v in range(wl["nvar"])),
         np.abs(gsrc - src).max() / max(np.abs(src).max(), 1.0)))
+    # divF is a difference of face fluxes that can cancel to far below the
+    # fluxes themselves: besides the relative bound, allow rounding of the
+    # face fluxes, 32 ulps of max|F| per unit of 1/dx
+    fmax = _flux_scale(o, wl, P)
+    idx = sum(wl["n"][d] / (wl["x_end"][d] - wl["x_start"][d]) for d in range(wl["ndim"]))
     for v in range(wl["nvar"]):
         scale = max(np.abs(dF[v]).max(), 1e-300)
-        assert np.abs(gdF[v] - dF[v]).max() <= tdf * scale + 1e-13, (v, np.abs(gdF[v] - dF[v]).max(), scale)
+        floor = 32 * np.finfo(float).eps * fmax[v] * idx
+        assert np.abs(gdF[v] - dF[v]).max() <= tdf * scale + floor, (v, np.abs(gdF[v] - dF[v]).max(), scale, floor)
     assert np.abs(gsrc - src).max() <= tsrc * max(np.abs(src).max(), 1.0)
     if wl["nvar"] == 10:
         for q in range(3):
@@ -221,14 +250,21 @@ def test_steps(torch_cuda, oracle_mod, name):
     gst = g.run(dt, nsteps, use_graph=True)
     gP = g.get_prims()
     assert gst["n_fail"] == st["n_fail"]
-    # zones that stop one iteration apart differ by up to the Newton tolerance
+    # Newton stops anywhere below the tolerance, so zones that stop one
+    # iteration apart differ by up to the tolerance, which is large against a
+    # family whose scale is the 1e-4 amplitude of a linear wave.  The bound is
+    # the oracle's own spread: under a rounding-level (1e-14) perturbation of
+    # its input (1e-9 in Kerr, where the geometry differs at that level), the
+    # largest over three draws, with the margin of 10 of _within_spread.
     err = prim_rel_err(gP, ref)
+    run = lambda Q: (o.step(Q, dt, nsteps)[0], None)
+    rel = 1e-9 if name in KERR else 1e-14
+    spread = np.max([_oracle_spread(run, P0, rel=rel, seed=sd, base=(ref, None))[0] for sd in (11, 12, 13)], axis=0)
+    _say(f"  max err {np.array2string(err.reshape(err.shape[0], -1).max(axis=1), precision=1)}")
+    _say(f"  oracle spread {np.array2string(spread, precision=1)}")
+    _within_spread(err, spread, 1e-6)
     if name in KERR:
-        spread, _ = _oracle_spread(lambda Q: (o.step(Q, dt, nsteps)[0], None), P0, base=(ref, None))
-        _say(f"  oracle spread {np.array2string(spread, precision=1)}")
-        _within_spread(err, spread, 1e-6)
         return
-    assert err.max() < 1e-6, err.max()
     for s in range(2):
         assert abs(gst["mean_iters"][s] - st["mean_iters"][s]) <= 0.01 * st["mean_iters"][s] + 1e-9
 
