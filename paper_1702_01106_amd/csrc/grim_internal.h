@@ -38,6 +38,19 @@ __device__ __forceinline__ void zone_ijk(const Layout& L, long z, int& i, int& j
     k = (int)kk;
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup b runs
+// on XCD b mod 8), and each XCD has its own L2.  xcd_block renumbers them so
+// that every XCD takes one contiguous eighth of the logical blocks: zones
+// whose stencils overlap then meet in the same L2 instead of being fetched
+// by several XCDs.  A bijection on [0, nb) for any nb.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned per = nb / kXcds, rem = nb % kXcds;  // XCDs x < rem take per + 1
+    const unsigned x = b % kXcds, i = b / kXcds;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 // Device-side accumulators of the solver statistics.  kStatCopies copies,
 // one 128-byte line each: a wave adds into copy (block index mod copies), so
 // no address sees more than 1/kStatCopies of the waves' atomics (atomics to

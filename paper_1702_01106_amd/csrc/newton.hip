@@ -496,7 +496,7 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
 template <int NV, class G, typename JT, int ND>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
-    const long z = (long)blockIdx.x * kWave + threadIdx.x;
+    const long z = (long)xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x;
     const bool retry = a.pass == 2;
     bool active = z < a.s.L.nz;
     if (retry) {
