@@ -163,7 +163,8 @@ int grim_cfl_dt(grim_ctx_t* ctx, double cfl, double* dt);
  * dt' = dt/2, then full step with P^E = P_{n+1/2}, dt' = dt; both Newton
  * solves start from P_n with B at its explicit update).  Asynchronous unless
  * stats != NULL, in which case the statistics of these steps are returned.
- * use_graph != 0 replays the step from a captured HIP graph. */
+ * use_graph != 0 replays captured HIP graphs of sixteen steps (and of one
+ * step for the remainder), captured on the first call for this dt. */
 int grim_run(grim_ctx_t* ctx, double dt, int nsteps, int use_graph, grim_stats_t* stats);
 
 /* Test hook for a8: the residual R(P) of every interior zone for a stage with

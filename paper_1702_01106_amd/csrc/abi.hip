@@ -59,7 +59,9 @@ struct grim_ctx {
     long mlp_idx_cap = 0;
     double* dloss = nullptr;
     size_t bytes = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // graph[p]: one step from state buffer p; graph[2 + p]: kGraphSteps steps
+    // from buffer p (an even count, so the step after it starts from p again)
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     double graph_dt = 0.0;
     bool timing = false;
     struct Mark {
@@ -113,7 +115,7 @@ void release(grim_ctx* c)
         hipEventDestroy(m.b);
     }
     c->marks.clear();
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
         if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->own_st && c->st) hipStreamDestroy(c->st);
@@ -534,6 +536,9 @@ int grim_cfl_dt(grim_ctx_t* c, double cfl, double* dt)
     return GRIM_OK;
 }
 
+// Steps per launch of the multi-step graph (even: the buffers ping-pong).
+constexpr int kGraphSteps = 16;
+
 int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* stats)
 {
     if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
@@ -543,15 +548,17 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
     HIP_TRY(c, grim::launch_zero_stats(c->stats, c->st));
     if (use_graph && nsteps > 0 && !c->timing) {
         if (c->graph_dt != dt || !c->graph[0]) {
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 4; ++i)
                 if (c->graph[i]) {
                     hipGraphExecDestroy(c->graph[i]);
                     c->graph[i] = nullptr;
                 }
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 4; ++i) {
                 hipGraph_t g = nullptr;
                 HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-                int rc = enqueue_step(c, i, dt, c->cap);
+                int rc = 0;
+                for (int s = 0; s < (i < 2 ? 1 : kGraphSteps) && rc == 0; ++s)
+                    rc = enqueue_step(c, (i + s) & 1, dt, c->cap);
                 hipError_t e = hipStreamEndCapture(c->cap, &g);
                 if (rc) {
                     if (g) hipGraphDestroy(g);
@@ -564,7 +571,11 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
             }
             c->graph_dt = dt;
         }
-        for (int s = 0; s < nsteps; ++s) {
+        // each graph launch costs ~8 us of idle GPU between graphs, so
+        // steps go kGraphSteps to a launch
+        int s = 0;
+        for (; s + kGraphSteps <= nsteps; s += kGraphSteps) HIP_TRY(c, hipGraphLaunch(c->graph[2 + c->cur], c->st));
+        for (; s < nsteps; ++s) {
             HIP_TRY(c, hipGraphLaunch(c->graph[c->cur], c->st));
             c->cur = 1 - c->cur;
         }
