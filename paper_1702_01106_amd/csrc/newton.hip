@@ -47,19 +47,22 @@ __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
             p = gt ? i : p;
         }
         ok = ok && (best != T(0));
-        // swap rows k and p with selects (J stays in registers)
+        // swap rows k and p with selects (J stays in registers), skipped
+        // when no active lane of the wave needs a swap at this step
+        if (k < N - 1 && __ballot(p != k) != 0ull) {
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
-            const bool s = (p == i);
+            for (int i = k + 1; i < N; ++i) {
+                const bool s = (p == i);
 #pragma unroll
-            for (int j = k; j < N; ++j) {
-                const T tk = A[k][j], ti = A[i][j];
-                A[k][j] = s ? ti : tk;
-                A[i][j] = s ? tk : ti;
+                for (int j = k; j < N; ++j) {
+                    const T tk = A[k][j], ti = A[i][j];
+                    A[k][j] = s ? ti : tk;
+                    A[i][j] = s ? tk : ti;
+                }
+                const T tk = b[k], ti = b[i];
+                b[k] = s ? ti : tk;
+                b[i] = s ? tk : ti;
             }
-            const T tk = b[k], ti = b[i];
-            b[k] = s ? ti : tk;
-            b[i] = s ? tk : ti;
         }
         inv[k] = rcp_nr(A[k][k]);
 #pragma unroll

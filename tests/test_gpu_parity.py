@@ -286,6 +286,25 @@ def test_graph_replays_match_eager(torch_cuda):
         assert np.array_equal(a.get_prims(), b.get_prims()), rep
 
 
+def test_multistep_graphs_match_eager(torch_cuda):
+    """Steps go sixteen to a graph launch plus single-step graphs for the
+    remainder; 17 then 20 steps cover a sixteen-step graph from each state
+    buffer and single steps from both.  Bit-identical to eager steps, also
+    in the statistics."""
+    wl = W.small("emhd2d_modes_256", [40, 36])
+    P0 = W.fourier_modes_2d(wl, seed=7, amp=1e-2)
+    a, b = _ctx(wl), _ctx(wl)
+    a.set_prims(P0)
+    b.set_prims(P0)
+    dt = a.cfl_dt(0.5)
+    for n in (17, 20):
+        sa = a.run(dt, n, use_graph=True, want_stats=True)
+        sb = b.run(dt, n, use_graph=False, want_stats=True)
+        torch_cuda.cuda.synchronize()
+        assert np.array_equal(a.get_prims(), b.get_prims()), n
+        assert sa["mean_iters"] == sb["mean_iters"] and sa["zone_stages"] == sb["zone_stages"], (sa, sb)
+
+
 def test_determinism(torch_cuda):
     wl = W.small("emhd2d_modes_256", [48, 40])
     P0 = W.fourier_modes_2d(wl, seed=6)
