@@ -63,6 +63,7 @@ struct grim_ctx {
     // from buffer p (an even count, so the step after it starts from p again)
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     double graph_dt = 0.0;
+    int cus = 0;  // compute units of the device
     bool timing = false;
     struct Mark {
         int group;
@@ -163,6 +164,19 @@ int validate(const grim_config_t* g, std::string& why)
 // Whether stage solves compute the right-hand side inside the Newton kernel.
 bool fused_rhs(const grim_ctx* c) { return c->cfg.metric == GRIM_MINKOWSKI; }
 
+// Whether a fused stage runs as the one tiled kernel (fluxes in LDS): 1- and
+// 2-D grids with the FP64 Jacobian (the FP32 form's FP64 retry pass reads
+// the fluxes from global memory), when the tiles fit the device in one
+// round (one 256-thread tile per CU).  Measured on the 2-D EMHD workload:
+// 28 us per stage against 33 us for the flux and Newton kernels at 256^2
+// (256 tiles), but 110 against 103 us at 512^2 (1024 tiles), where each CU
+// runs four tiles one after another.
+bool tiled_stage(const grim_ctx* c)
+{
+    return fused_rhs(c) && c->cfg.ndim <= 2 && c->cfg.jac_precision == GRIM_JAC_F64 &&
+           grim::stage_tiles(c->L) <= (long)c->cus;
+}
+
 StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)
 {
     StageArgs a{};
@@ -245,7 +259,8 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     // Minkowski without the network's features: the Newton kernel computes
     // each zone's right-hand side itself (no rhs kernel, no rhs round trip)
     const bool fused = fused_rhs(c) && !net && !col;
-    {
+    const bool tiled = fused && tiled_stage(c);
+    if (!tiled) {
         Timed t(c, 1, st);
         HIP_TRY(c, grim::launch_fluxes(s, c->nvar, c->cfg.metric, st));
     }
@@ -262,6 +277,7 @@ int enqueue_stage(grim_ctx* c, double* Pn, double* PE, double dtp, double* out, 
     n.out_ghosted = 1;
     n.write_ghosts = 1;  // the output's ghosts are written with it
     n.fused = fused ? 1 : 0;
+    n.tiled = tiled ? 1 : 0;
     n.stage = stage;
     n.mlp_y = net ? c->mlp_y : nullptr;
     {
@@ -396,6 +412,12 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
             delete c;
             return GRIM_E_HIP;
         }
+    }
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            c->cus = 0;
     }
     c->nvar = cfg->model;
     Layout& L = c->L;
@@ -638,6 +660,7 @@ int grim_stage_solve(grim_ctx_t* c, const double* Pn, const double* PE, double d
     n.out = P_out;
     n.out_ghosted = 0;
     n.fused = fused_rhs(c) ? 1 : 0;  // the same Newton kernel grim_run uses
+    n.tiled = tiled_stage(c) ? 1 : 0;
     n.stage = 0;
     if (iters) n.iters = iters;
     if (resid) n.resid = resid;

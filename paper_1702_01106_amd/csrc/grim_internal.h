@@ -165,6 +165,10 @@ struct NewtonArgs {
     // the face fluxes (fused), instead of reading what the rhs kernel stored
     // (Minkowski only; ignored for Kerr)
     int fused;
+    // with fused, 1- and 2-D, FP64 Jacobian and no network: one kernel per
+    // stage that computes a tile's face fluxes into LDS, then solves its
+    // zones (the flux kernel is not launched)
+    int tiled;
 };
 constexpr uint8_t kFlagRetry = 32;
 
@@ -174,6 +178,8 @@ hipError_t launch_explicit_stage(const StageArgs& a, int nvar, int metric, hipSt
 hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st);
+// blocks (tiles) of the tiled stage kernel for a 1- or 2-D layout
+long stage_tiles(const Layout& L);
 hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const double* P, double* R, double* rnorm,
                            hipStream_t st);
 hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int nvar, int metric, const double* P,

@@ -10,25 +10,73 @@
 
 namespace grim {
 
-// Flux-CT (Sec. 4.2): the edge EMF as the average of the four face B-fluxes
-// around the edge.  E (index e) at cell c: E3 on (i-1/2, j-1/2, k), E1 on
-// (i, j-1/2, k-1/2), E2 on (i-1/2, j, k-1/2).  Evaluated where the stage
-// right-hand side needs it, from the face fluxes.
-template <int E>
-__device__ __forceinline__ double edge_emf(const StageArgs& a, long c)
+// LLF flux of every variable through one face normal to DIR (Sec. 2.4):
+// left/right states by generalized-minmod PLM of the four P^E cells along DIR
+// around the face, c_max the largest |speed| of either state.  cell(v, o) is
+// variable v of the cell at offset o in {-2, -1, 0, 1} from the face's high
+// cell.  The normal B flux is exactly zero.
+template <int NV, class G, int DIR, class Cell>
+__device__ __forceinline__ void llf_face(const Phys& ph, const G& g, const Cell& cell, double* f)
 {
-    const Layout& L = a.L;
-    const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
-    const long C = L.cells;
-    const double* F1 = a.F[0];
-    const double* F2 = a.F[1];
-    const double* F3 = a.F[2];
+    const double th = ph.theta;
+    double PL[NV], PR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double pm2 = cell(v, -2), pm1 = cell(v, -1), p0 = cell(v, 0), pp1 = cell(v, 1);
+        PL[v] = pm1 + 0.5 * gmm(pm1 - pm2, p0 - pm1, th);
+        PR[v] = p0 - 0.5 * gmm(p0 - pm1, pp1 - p0, th);
+    }
+    St<NV> sL, sR;
+    derive<NV>(PL, g, ph, sL);
+    derive<NV>(PR, g, ph, sR);
+    const double c = fmax(cmax<NV, DIR>(PL, g, sL, ph), cmax<NV, DIR>(PR, g, sR, ph));
+    double UL[NV], UR[NV], FL[NV], FR[NV];
+    conserved<NV>(PL, g, sL, ph, UL);
+    conserved<NV>(PR, g, sR, ph, UR);
+    flux<NV, DIR>(PL, g, sL, ph, FL);
+    flux<NV, DIR>(PR, g, sR, ph, FR);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
+}
+
+// Where zone_rhs reads the face fluxes, P^E and P_n: F(d, v, m, o) is the
+// flux of variable v through the face normal to d on the low side of the cell
+// at offset o = (o1, o2, o3) from cell m; PE(v, m, o) is P^E there; Pn(v, m)
+// is P_n of cell m.  SrcGlobal reads the stage buffers; the tiled stage
+// kernel reads its LDS tile and the P_n it loaded ahead.
+struct SrcGlobal {
+    const StageArgs& a;
+    __device__ __forceinline__ long at(long m, int o1, int o2, int o3) const
+    {
+        return m + o1 + (long)o2 * a.L.N[0] + (long)o3 * a.L.N[0] * a.L.N[1];
+    }
+    __device__ __forceinline__ double F(int d, int v, long m, int o1, int o2, int o3) const
+    {
+        return a.F[d][(long)v * a.L.cells + at(m, o1, o2, o3)];
+    }
+    __device__ __forceinline__ double PE(int v, long m, int o1, int o2, int o3) const
+    {
+        return a.PE[(long)v * a.L.cells + at(m, o1, o2, o3)];
+    }
+    __device__ __forceinline__ double Pn(int v, long m) const { return a.Pn[(long)v * a.L.cells + m]; }
+};
+
+// Flux-CT (Sec. 4.2): the edge EMF as the average of the four face B-fluxes
+// around the edge.  E (index e) at the cell at offset o from m: E3 on
+// (i-1/2, j-1/2, k), E1 on (i, j-1/2, k-1/2), E2 on (i-1/2, j, k-1/2).
+// Evaluated where the stage right-hand side needs it, from the face fluxes.
+template <int E, class Src>
+__device__ __forceinline__ double edge_emf(const Src& f, long m, int o1, int o2, int o3)
+{
     if constexpr (E == 2)
-        return 0.25 * (F1[B2 * C + c] + F1[B2 * C + c - s2] - F2[B1 * C + c] - F2[B1 * C + c - s1]);
+        return 0.25 * (f.F(0, B2, m, o1, o2, o3) + f.F(0, B2, m, o1, o2 - 1, o3) - f.F(1, B1, m, o1, o2, o3) -
+                       f.F(1, B1, m, o1 - 1, o2, o3));
     else if constexpr (E == 0)
-        return 0.25 * (F2[B3 * C + c] + F2[B3 * C + c - s3] - F3[B2 * C + c] - F3[B2 * C + c - s2]);
+        return 0.25 * (f.F(1, B3, m, o1, o2, o3) + f.F(1, B3, m, o1, o2, o3 - 1) - f.F(2, B2, m, o1, o2, o3) -
+                       f.F(2, B2, m, o1, o2 - 1, o3));
     else
-        return 0.25 * (F3[B1 * C + c] + F3[B1 * C + c - s1] - F1[B3 * C + c] - F1[B3 * C + c - s3]);
+        return 0.25 * (f.F(2, B1, m, o1, o2, o3) + f.F(2, B1, m, o1 - 1, o2, o3) - f.F(0, B3, m, o1, o2, o3) -
+                       f.F(0, B3, m, o1, o2, o3 - 1));
 }
 
 // ------------------------------------------------------------------ stage rhs
@@ -61,8 +109,8 @@ __device__ __forceinline__ void load_cell(const double* P, long cells, long m, d
 // needs (bhat^mu of P^E, Theta(P_n), u^0(P_n), bhat.u(P_n), aq1, aq2, aq3,
 // ad2, ad3, chalf).  g returns the zone's metric.  With kOut the optional
 // outputs of a (learned-guess features, test-hook arrays) are written too.
-template <int NV, class G, int ND, bool kOut>
-__device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs, double* co, G& g)
+template <int NV, class G, int ND, bool kOut, class Src>
+__device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs, double* co, G& g, const Src& in)
 {
     const Layout& L = a.L;
     int ii, jj, kk;
@@ -79,27 +127,33 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         double s = 0.0;
 #pragma unroll
         for (int d = 0; d < nd; ++d) {
-            const long st = L.stride(d);
+            // offset of the high face's cell
+            const int e1 = d == 0, e2 = d == 1, e3 = d == 2;
             double fr, fl;
             const bool ct = nd >= 2 && v >= B1 && v <= B3 && (nd == 3 || v != B3);
             if (!ct) {
-                fr = a.F[d][(long)v * C + m + st];
-                fl = a.F[d][(long)v * C + m];
+                fr = in.F(d, v, m, e1, e2, e3);
+                fl = in.F(d, v, m, 0, 0, 0);
             } else {
                 const int b = v - B1;
-                const long s1 = 1, s2 = L.N[0], s3 = (long)L.N[0] * L.N[1];
-                // face B^b flux through faces normal to d, from the edge EMFs
-                auto face = [&](long c) -> double {
+                // face B^b flux through the face normal to d of the cell at
+                // offset o, from the edge EMFs
+                auto face = [&](int o1, int o2, int o3) -> double {
                     if (b == d) return 0.0;
-                    if (d == 0 && b == 1) return 0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s2));
-                    if (d == 0 && b == 2) return -0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s3));
-                    if (d == 1 && b == 0) return -0.5 * (edge_emf<2>(a, c) + edge_emf<2>(a, c + s1));
-                    if (d == 1 && b == 2) return 0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s3));
-                    if (d == 2 && b == 0) return 0.5 * (edge_emf<1>(a, c) + edge_emf<1>(a, c + s1));
-                    return -0.5 * (edge_emf<0>(a, c) + edge_emf<0>(a, c + s2));  // d == 2 && b == 1
+                    if (d == 0 && b == 1)
+                        return 0.5 * (edge_emf<2>(in, m, o1, o2, o3) + edge_emf<2>(in, m, o1, o2 + 1, o3));
+                    if (d == 0 && b == 2)
+                        return -0.5 * (edge_emf<1>(in, m, o1, o2, o3) + edge_emf<1>(in, m, o1, o2, o3 + 1));
+                    if (d == 1 && b == 0)
+                        return -0.5 * (edge_emf<2>(in, m, o1, o2, o3) + edge_emf<2>(in, m, o1 + 1, o2, o3));
+                    if (d == 1 && b == 2)
+                        return 0.5 * (edge_emf<0>(in, m, o1, o2, o3) + edge_emf<0>(in, m, o1, o2, o3 + 1));
+                    if (d == 2 && b == 0)
+                        return 0.5 * (edge_emf<1>(in, m, o1, o2, o3) + edge_emf<1>(in, m, o1 + 1, o2, o3));
+                    return -0.5 * (edge_emf<0>(in, m, o1, o2, o3) + edge_emf<0>(in, m, o1, o2 + 1, o3));  // d == 2, b == 1
                 };
-                fr = face(m + st);
-                fl = face(m);
+                fr = face(e1, e2, e3);
+                fl = face(0, 0, 0);
             }
             s += (fr - fl) * (1.0 / L.dx[d]);
         }
@@ -109,8 +163,11 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
     if constexpr (!G::kFlat) load_geo(g, a.geo.centre, (size_t)((long)j * L.N[0] + i), a.geo.stride);
     const double idt = 1.0 / a.dtp;
     double Pn[NV], PE[NV];
-    load_cell<NV>(a.Pn, C, m, Pn);
-    load_cell<NV>(a.PE, C, m, PE);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        Pn[v] = in.Pn(v, m);
+        PE[v] = in.PE(v, m, 0, 0, 0);
+    }
     St<NV> sn, sE;
     derive<NV>(Pn, g, a.ph, sn);
     derive<NV>(PE, g, a.ph, sE);
@@ -175,10 +232,13 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
 #pragma unroll
         for (int d = 0; d < nd; ++d) {
             const double bhd = sE.bh[d + 1], ud = sE.ucon[d + 1];
-            const long st = L.stride(d);
+            const int e1 = d == 0, e2 = d == 1, e3 = d == 2;
             double Pm[NV], Pp[NV], Xm[8], Xp[8];
-            load_cell<NV>(a.PE, C, m - st, Pm);
-            load_cell<NV>(a.PE, C, m + st, Pp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Pm[v] = in.PE(v, m, -e1, -e2, -e3);
+                Pp[v] = in.PE(v, m, e1, e2, e3);
+            }
             G gm, gp;
             if constexpr (!G::kFlat) {
                 const int im = d == 0 ? i - 1 : i, jm = d == 1 ? j - 1 : j;

@@ -60,41 +60,21 @@ __global__ __launch_bounds__(kBlock) void k_fill_ghosts(Layout L, int nvar, int 
 
 // ------------------------------------------------------------------ fluxes
 
-// The face on the low side of cell (i, j, k) in direction DIR.  Left/right
-// states by generalized-minmod PLM of the four cells along DIR, then LLF with
-// c_max the largest |speed| of either state.
+// The face on the low side of cell (i, j, k) in direction DIR (llf_face),
+// read from and stored to the stage buffers.
 template <int NV, class G, int DIR>
 __device__ __forceinline__ void face_flux(const StageArgs& a, int i, int j, int k)
 {
     const Layout& L = a.L;
     const long m = L.cell(i, j, k);
     const long st = L.stride(DIR - 1);
-    const double th = a.ph.theta;
-    double PL[NV], PR[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double* p = a.PE + (long)v * L.cells + m;
-        const double pm2 = p[-2 * st], pm1 = p[-st], p0 = p[0], pp1 = p[st];
-        PL[v] = pm1 + 0.5 * gmm(pm1 - pm2, p0 - pm1, th);
-        PR[v] = p0 - 0.5 * gmm(p0 - pm1, pp1 - p0, th);
-    }
     G g;
     if constexpr (!G::kFlat) load_geo(g, a.geo.face[DIR - 1], (size_t)((long)j * L.N[0] + i), a.geo.stride);
-    St<NV> sL, sR;
-    derive<NV>(PL, g, a.ph, sL);
-    derive<NV>(PR, g, a.ph, sR);
-    const double c = fmax(cmax<NV, DIR>(PL, g, sL, a.ph), cmax<NV, DIR>(PR, g, sR, a.ph));
-    double UL[NV], UR[NV], FL[NV], FR[NV];
-    conserved<NV>(PL, g, sL, a.ph, UL);
-    conserved<NV>(PR, g, sR, a.ph, UR);
-    flux<NV, DIR>(PL, g, sL, a.ph, FL);
-    flux<NV, DIR>(PR, g, sR, a.ph, FR);
+    double f[NV];
+    llf_face<NV, G, DIR>(a.ph, g, [&](int v, int o) { return a.PE[(long)v * L.cells + m + o * st]; }, f);
     double* F = a.F[DIR - 1];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double f = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
-        F[(long)v * L.cells + m] = f;
-    }
+    for (int v = 0; v < NV; ++v) F[(long)v * L.cells + m] = f[v];
 }
 
 // Face ranges of every active direction in one launch: blocks
@@ -136,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
     if (z >= a.L.nz) return;
     double rhs[NV], co[kEmhdCoef];
     G g;
-    zone_rhs<NV, G, ND, true>(a, z, rhs, co, g);
+    zone_rhs<NV, G, ND, true>(a, z, rhs, co, g, SrcGlobal{a});
     const long nz = a.L.nz;
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.rhs[(long)v * nz + z] = rhs[v];

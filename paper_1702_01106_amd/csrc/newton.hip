@@ -247,9 +247,9 @@ struct ZoneSolve {
 // B at its explicit update (the exact root of the B rows), the learned
 // candidate if one is given and its residual is smaller, and the initial
 // residual.
-template <int NV, class G, int ND>
+template <int NV, class G, int ND, class Src = SrcGlobal>
 __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const double* guess, const float* mlp_y,
-                                         ZoneSolve<NV, G>& s)
+                                         ZoneSolve<NV, G>& s, const Src* in = nullptr)
 {
     const Layout& L = a.s.L;
     const Phys& ph = a.s.ph;
@@ -259,7 +259,10 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
         load_zone<NV, G>(a.s, z, s.cell, s.zc);
     } else {
         double co[kEmhdCoef];
-        zone_rhs<NV, G, ND, false>(a.s, z, s.zc.rhs, co, s.zc.g);
+        if constexpr (__is_same(Src, SrcGlobal))
+            zone_rhs<NV, G, ND, false>(a.s, z, s.zc.rhs, co, s.zc.g, SrcGlobal{a.s});
+        else
+            zone_rhs<NV, G, ND, false>(a.s, z, s.zc.rhs, co, s.zc.g, *in);
         zone_from_rhs<NV, G>(a.s, co, s.zc);
     }
     s.fB = a.s.dtp / s.zc.g.gdet();
@@ -273,7 +276,12 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
     {
         double pn[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * L.cells + s.cell];
+        for (int v = 0; v < NV; ++v) {
+            if constexpr (__is_same(Src, SrcGlobal))
+                pn[v] = a.s.Pn[(long)v * L.cells + s.cell];
+            else
+                pn[v] = in->Pn(v, s.cell);
+        }
         St<NV> sn;
         derive<NV>(pn, s.zc.g, ph, sn);
         // scaled norm: ||R|| = dt' sqrt(sum R^2) / U_rho(P_n)
@@ -517,6 +525,146 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     if (a.stats) flush_stats(a, ls);
 }
 
+// ------------------------------------------------------------------ tiled stage
+//
+// One kernel per stage for 1- and 2-D Minkowski grids: a block of 256 threads
+// owns a tile of TX x TY zones.  It stages the tile's P^E with a two-cell halo
+// in LDS, computes into LDS every face flux its zones need (the x-faces of
+// rows -1..TY, for the corner EMFs of flux-CT, and the y-faces of columns
+// -1..TX), then solves one zone per thread, reading fluxes and P^E from LDS.
+// Fluxes never go to global memory and the stage is one launch; the price is
+// recomputing the faces shared with neighbouring tiles (2.8 faces per zone in
+// 2-D against 2.0).
+template <int ND>
+struct Tile {
+    static constexpr int TX = ND == 1 ? 256 : 64, TY = ND == 1 ? 1 : 4;
+    static constexpr int HY = ND == 1 ? 0 : 2;                     // P^E halo rows per side
+    static constexpr int PX = TX + 4, PY = TY + 2 * HY;            // P^E tile, origin at (-2, -HY)
+    static constexpr int XX = TX + 1, XY = ND == 1 ? 1 : TY + 2;   // x-faces: columns 0..TX, rows -1..TY
+    static constexpr int XR = ND == 1 ? 0 : 1;                     // row offset of the x-face tile
+    static constexpr int YX = TX + 2, YY = ND == 1 ? 0 : TY + 1;   // y-faces: columns -1..TX, rows 0..TY
+    static constexpr int kThreads = TX * TY;
+    template <int NV>
+    static constexpr int words() { return NV * (PX * PY + XX * XY + YX * YY); }
+};
+
+template <int NV, int ND>
+struct SrcTile {
+    using T = Tile<ND>;
+    const double* pe;  // [NV][PY][PX]
+    const double* fx;  // [NV][XY][XX]
+    const double* fy;  // [NV][YY][YX]
+    const double* pn;  // P_n of the zone (registers)
+    int lx, ly;        // the zone in the tile
+    __device__ __forceinline__ double F(int d, int v, long, int o1, int o2, int) const
+    {
+        if (d == 0) return fx[(v * T::XY + ly + o2 + T::XR) * T::XX + lx + o1];
+        return fy[(v * T::YY + ly + o2) * T::YX + lx + o1 + 1];
+    }
+    __device__ __forceinline__ double PE(int v, long, int o1, int o2, int) const
+    {
+        return pe[(v * T::PY + ly + o2 + T::HY) * T::PX + lx + o1 + 2];
+    }
+    __device__ __forceinline__ double Pn(int v, long) const { return pn[v]; }
+};
+
+template <int NV, int ND>
+__global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
+{
+    using T = Tile<ND>;
+    __shared__ double lds[T::template words<NV>()];
+    double* pe = lds;
+    double* fx = pe + NV * T::PY * T::PX;
+    double* fy = fx + NV * T::XY * T::XX;
+    const Layout& L = a.s.L;
+    const long C = L.cells;
+    const int tid = threadIdx.x;
+    const unsigned tb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned ntx = (unsigned)((L.n[0] + T::TX - 1) / T::TX);
+    const int x0 = (int)(tb % ntx) * T::TX, y0 = (int)(tb / ntx) * T::TY;  // interior coordinates
+    const int w = min(T::TX, L.n[0] - x0), h = ND == 1 ? 1 : min(T::TY, L.n[1] - y0);
+    const int lx = tid % T::TX, ly = tid / T::TX;
+    const bool active = lx < w && ly < h;
+    const long z = (long)(y0 + ly) * L.n[0] + x0 + lx;
+    // the zone's P_n, read now so that its latency hides behind the tile work
+    double pn[NV];
+    if (active) {
+        const long m = L.cell(x0 + lx + L.g[0], y0 + ly + L.g[1], 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * C + m];
+    }
+
+    // P^E of the tile and its halo, every read issued before the first LDS
+    // write; cells past the ghosted grid (ragged tiles) are not needed
+    {
+        const int gi0 = x0 + L.g[0] - 2, gj0 = y0 + L.g[1] - T::HY;
+        constexpr int n = NV * T::PY * T::PX, per = (n + T::kThreads - 1) / T::kThreads;
+        double b[per];
+#pragma unroll
+        for (int r = 0; r < per; ++r) {
+            const int q = tid + r * T::kThreads;
+            const int v = q / (T::PY * T::PX), rr = (q / T::PX) % T::PY, c = q % T::PX;
+            const int gi = gi0 + c, gj = gj0 + rr;
+            b[r] = (q < n && gi < L.N[0] && gj < L.N[1]) ? a.s.PE[(long)v * C + L.cell(gi, gj, 0)] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < per; ++r)
+            if (tid + r * T::kThreads < n) pe[tid + r * T::kThreads] = b[r];
+    }
+    __syncthreads();
+
+    // the tile's face fluxes: x-face q and y-face q of a thread are
+    // independent and computed together (two chains in flight per lane)
+    constexpr int nxf = T::XX * T::XY, nyf = T::YX * T::YY;
+    const Phys& ph = a.s.ph;
+    const GeoMink g{};
+    for (int q = tid; q < (nxf > nyf ? nxf : nyf); q += T::kThreads) {
+        double f[NV], e[NV];
+        const int cx = q % T::XX, cy = q / T::XX - T::XR;
+        const bool dx = q < nxf && cx <= w && cy <= (ND == 1 ? 0 : h);
+        const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
+        if (dx) llf_face<NV, GeoMink, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, f);
+        if constexpr (ND >= 2) {
+            const int ex = q % T::YX - 1, ey = q / T::YX;
+            const bool dy = q < nyf && ex <= w && ey <= h;
+            const double* pq = pe + (ey + T::HY) * T::PX + ex + 2;
+            if (dy) {
+                llf_face<NV, GeoMink, 2>(ph, g, [&](int v, int o) { return pq[v * T::PY * T::PX + o * T::PX]; }, e);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = e[v];
+            }
+        }
+        if (dx) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fx[(v * T::XY + cy + T::XR) * T::XX + cx] = f[v];
+        }
+    }
+    __syncthreads();
+
+    // one zone per thread; a wave is 64 zones of one row
+    LaneStats ls;
+    if (active) {
+        const SrcTile<NV, ND> in{pe, fx, fy, pn, lx, ly};
+        ZoneSolve<NV, GeoMink> s;
+        zs_begin<NV, GeoMink, ND>(a, z, a.guess, nullptr, s, &in);
+        while (!zs_step<NV, GeoMink, double>(a, s)) {
+        }
+        zs_finish<NV, GeoMink>(a, s, false, ls);
+    }
+    if (a.stats) flush_stats(a, ls);
+}
+
+template <int NV, int ND>
+hipError_t stage_tiled(const NewtonArgs& a, hipStream_t st)
+{
+    using T = Tile<ND>;
+    const long tiles = (long)((a.s.L.n[0] + T::TX - 1) / T::TX) * ((a.s.L.n[1] + T::TY - 1) / T::TY);
+    NewtonArgs b = a;
+    b.pass = 0;
+    hipLaunchKernelGGL((k_stage<NV, ND>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
+    return hipGetLastError();
+}
+
 template <int NV, class G, int ND>
 hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
@@ -545,6 +693,8 @@ template <int NV, class G>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     if constexpr (G::kFlat) {
+        if (a.fused && a.tiled && !jac_f32 && !a.mlp_y && a.s.L.ndim <= 2)
+            return a.s.L.ndim == 1 ? stage_tiled<NV, 1>(a, st) : stage_tiled<NV, 2>(a, st);
         if (a.fused) {
             switch (a.s.L.ndim) {
                 case 1: return newton_nd<NV, G, 1>(a, jac_f32, st);
@@ -557,6 +707,12 @@ hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 }
 
 }  // namespace
+
+long stage_tiles(const Layout& L)
+{
+    if (L.ndim == 1) return (L.n[0] + Tile<1>::TX - 1) / Tile<1>::TX;
+    return (long)((L.n[0] + Tile<2>::TX - 1) / Tile<2>::TX) * ((L.n[1] + Tile<2>::TY - 1) / Tile<2>::TY);
+}
 
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st)
 {
