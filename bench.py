@@ -39,6 +39,19 @@ HBM_PEAK_GBS = 8000.0
 RESID_FLOPS = {8: 66, 10: 157}
 LU_FLOPS = {5: 133, 7: 327}
 
+# FP64 operations of one face flux in Minkowski coordinates (same counting):
+# PLM of every variable (15 per variable: three differences, two
+# generalized-minmod slopes, two half-slope updates), and per state derive
+# (41 EMHD / 31 ideal), wave speed (41 / 33), U (76 / 20) and F (73 / 26),
+# then LLF (5 per non-normal variable).
+FACE_FLOPS = {8: 376, 10: 658}
+# FP64 operations of one zone's stage right-hand side on a 2-D grid: flux
+# divergence with the flux-CT EMFs (~100 EMHD), U(P_n) and the derived
+# states of P_n and P^E (158), and for EMHD the limited slopes of Theta, u_mu
+# and u^i from the four neighbours and the folded relaxation coefficients
+# (434); ideal MHD ~180 in all.
+RHS_FLOPS_2D = {8: 180, 10: 712}
+
 
 def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) -> float:
     """Algorithmic FP64 flops of the Newton solves summed over a run (the
@@ -52,7 +65,7 @@ def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) ->
             + ls_trials * 2 * n)
 
 
-NEWTON_SOURCES = ["newton.hip", "grim_zone.h", "grim_device.h", "grim_internal.h"]
+NEWTON_SOURCES = ["newton.hip", "grim_zone.h", "grim_device.h", "grim_internal.h", "grim_rhs.h"]
 
 
 def newton_source_hash() -> str:
@@ -261,6 +274,14 @@ def main() -> int:
     flops = newton_flops(nvar, st_p["zone_stages"], (st_p["mean_iters"][0] + st_p["mean_iters"][1]) * zones
                          * args.steps, st_p["n_resid_calls"])
     per_launch_flops = flops / max(n_newton, 1)
+    # on a 1- or 2-D Minkowski grid whose tiles fit the device the stage is
+    # one kernel (faces, right-hand side and Newton); its algorithmic flops
+    # count every face once and every zone's right-hand side once
+    tiled = times.get("face_flux", (0.0, 0))[1] == 0 and wl["ndim"] == 2 and wl["metric"] == "minkowski"
+    if tiled:
+        n = list(wl["n"])
+        faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1)
+        per_launch_flops += faces * FACE_FLOPS[nvar] + zones * RHS_FLOPS_2D[nvar]
     avg_s = ms_newton / max(n_newton, 1) * 1e-3
     achieved = per_launch_flops / avg_s / 1e12
     roofline = {
@@ -270,7 +291,8 @@ def main() -> int:
         "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
         "traffic": traffic_from_profiles(),
-        "kernel": f"k_newton<{nvar}, Minkowski, f64>",
+        "kernel": (f"k_stage<{nvar}, 2> (tile face fluxes + stage right-hand side + Newton, f64)" if tiled
+                   else f"k_newton<{nvar}, Minkowski, f64>"),
         "avg_launch_us": avg_s * 1e6,
         "flops_per_launch": per_launch_flops,
     }

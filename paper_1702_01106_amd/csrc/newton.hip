@@ -528,16 +528,17 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 // ------------------------------------------------------------------ tiled stage
 //
 // One kernel per stage for 1- and 2-D Minkowski grids: a block of 256 threads
-// owns a tile of TX x TY zones.  It stages the tile's P^E with a two-cell halo
-// in LDS, computes into LDS every face flux its zones need (the x-faces of
-// rows -1..TY, for the corner EMFs of flux-CT, and the y-faces of columns
-// -1..TX), then solves one zone per thread, reading fluxes and P^E from LDS.
+// owns a tile of TX x TY zones (16 x 16 in 2-D, 256 in 1-D).  It stages the
+// tile's P^E with a two-cell halo in LDS, computes into LDS every face flux
+// its zones need (the x-faces of rows -1..TY, for the corner EMFs of
+// flux-CT, and the y-faces of columns -1..TX), then solves one zone per
+// thread, reading fluxes and P^E from LDS.
 // Fluxes never go to global memory and the stage is one launch; the price is
-// recomputing the faces shared with neighbouring tiles (2.8 faces per zone in
+// recomputing the faces shared with neighbouring tiles (2.4 faces per zone in
 // 2-D against 2.0).
 template <int ND>
 struct Tile {
-    static constexpr int TX = ND == 1 ? 256 : 64, TY = ND == 1 ? 1 : 4;
+    static constexpr int TX = ND == 1 ? 256 : 16, TY = ND == 1 ? 1 : 16;
     static constexpr int HY = ND == 1 ? 0 : 2;                     // P^E halo rows per side
     static constexpr int PX = TX + 4, PY = TY + 2 * HY;            // P^E tile, origin at (-2, -HY)
     static constexpr int XX = TX + 1, XY = ND == 1 ? 1 : TY + 2;   // x-faces: columns 0..TX, rows -1..TY
@@ -613,35 +614,50 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
     }
     __syncthreads();
 
-    // the tile's face fluxes: x-face q and y-face q of a thread are
-    // independent and computed together (two chains in flight per lane)
+    // the tile's face fluxes.  First every thread computes x-face t and
+    // y-face t together, unconditionally (indices clamped into the tile, so a
+    // face not needed reads defined LDS and is simply not stored): two
+    // independent chains per lane in one basic block.  The remaining faces
+    // go to waves 0-1 (x) and 2-3 (y), so no wave computes more than three.
     constexpr int nxf = T::XX * T::XY, nyf = T::YX * T::YY;
+    static_assert(nxf - T::kThreads <= T::kThreads / 2 && nyf - T::kThreads <= T::kThreads / 2, "face split");
     const Phys& ph = a.s.ph;
     const GeoMink g{};
-    for (int q = tid; q < (nxf > nyf ? nxf : nyf); q += T::kThreads) {
-        double f[NV], e[NV];
+    auto xface = [&](int q, bool keep) {
         const int cx = q % T::XX, cy = q / T::XX - T::XR;
-        const bool dx = q < nxf && cx <= w && cy <= (ND == 1 ? 0 : h);
         const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
-        if (dx) llf_face<NV, GeoMink, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, f);
-        if constexpr (ND >= 2) {
-            const int ex = q % T::YX - 1, ey = q / T::YX;
-            const bool dy = q < nyf && ex <= w && ey <= h;
-            const double* pq = pe + (ey + T::HY) * T::PX + ex + 2;
-            if (dy) {
-                llf_face<NV, GeoMink, 2>(ph, g, [&](int v, int o) { return pq[v * T::PY * T::PX + o * T::PX]; }, e);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = e[v];
-            }
-        }
-        if (dx) {
+        double f[NV];
+        llf_face<NV, GeoMink, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, f);
+        if (keep && cx <= w && cy <= (ND == 1 ? 0 : h)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) fx[(v * T::XY + cy + T::XR) * T::XX + cx] = f[v];
         }
+    };
+    auto yface = [&](int q, bool keep) {
+        const int ex = q % T::YX - 1, ey = q / T::YX;
+        const double* p = pe + (ey + T::HY) * T::PX + ex + 2;
+        double f[NV];
+        llf_face<NV, GeoMink, 2>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o * T::PX]; }, f);
+        if (keep && ex <= w && ey <= h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = f[v];
+        }
+    };
+    if constexpr (ND >= 2) {
+        xface(min(tid, nxf - 1), tid < nxf);
+        yface(min(tid, nyf - 1), tid < nyf);
+        if (tid < T::kThreads / 2) {
+            if (tid < nxf - T::kThreads) xface(T::kThreads + tid, true);
+        } else if (tid - T::kThreads / 2 < nyf - T::kThreads) {
+            yface(tid - T::kThreads / 2 + T::kThreads, true);
+        }
+    } else {
+        xface(tid, true);
+        if (tid < nxf - T::kThreads) xface(T::kThreads + tid, true);
     }
     __syncthreads();
 
-    // one zone per thread; a wave is 64 zones of one row
+    // one zone per thread; a wave is four rows of 16 zones (2-D)
     LaneStats ls;
     if (active) {
         const SrcTile<NV, ND> in{pe, fx, fy, pn, lx, ly};
