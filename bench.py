@@ -65,29 +65,29 @@ def newton_flops(nvar: int, zone_stages: int, iters: float, resid_calls: int) ->
             + ls_trials * 2 * n)
 
 
-NEWTON_SOURCES = ["newton.hip", "grim_zone.h", "grim_device.h", "grim_internal.h", "grim_rhs.h"]
+STAGE_SOURCES = ["newton.hip", "grim_zone.h", "grim_device.h", "grim_internal.h", "grim_rhs.h"]
 
 
-def newton_source_hash() -> str:
-    """Hash of the sources the Newton kernel is compiled from."""
+def stage_source_hash() -> str:
+    """Hash of the sources the stage (and Newton) kernels are compiled from."""
     h = hashlib.sha256()
-    for f in NEWTON_SOURCES:
+    for f in STAGE_SOURCES:
         with open(os.path.join(ROOT, "paper_1702_01106_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profiles():
-    """HBM bytes per Newton launch from committed rocprofv3 counters, if they
-    were taken on the current kernel sources; otherwise None."""
-    p = os.path.join(ROOT, "profiles", "newton_emhd2d_256_traffic.json")
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counters, if they were taken on the current kernel sources; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "stage_emhd2d_256_traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
-    if d.get("newton_source_sha256_16") != newton_source_hash():
+    if d.get("source_sha256_16") != stage_source_hash():
         return None
     return d.get("bytes_per_launch")
 
@@ -143,7 +143,10 @@ def timed_run(grim, W, wl, P0, steps, warmup, weights=None):
     kernel times and the final primitives of the timed run."""
     import torch
 
-    ctx = grim.Context(wl)
+    # the library runs on torch's current stream, so that torch's events
+    # bracket the graph-replayed steps on the stream they run on
+    stream = torch.cuda.current_stream()
+    ctx = grim.Context(wl, stream=stream)
     if weights is not None:
         grim.grim_mlp_set_weights(ctx.ctx, weights)
     ctx.set_prims(P0)
@@ -151,11 +154,15 @@ def timed_run(grim, W, wl, P0, steps, warmup, weights=None):
     if warmup > 0:
         ctx.run(dt, warmup, use_graph=True)
     ctx.set_prims(P0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record(stream)
     st = ctx.run(dt, steps, use_graph=True, want_stats=True)
+    e1.record(stream)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    st["event_seconds"] = e0.elapsed_time(e1) * 1e-3
     P_end = ctx.get_prims()
     # instrumented eager pass over the same steps: per-kernel device time
     ctx.set_prims(P0)
@@ -283,6 +290,11 @@ def main() -> int:
         faces = (n[0] + 1) * n[1] + n[0] * (n[1] + 1)
         per_launch_flops += faces * FACE_FLOPS[nvar] + zones * RHS_FLOPS_2D[nvar]
     avg_s = ms_newton / max(n_newton, 1) * 1e-3
+    if tiled:
+        # the timed region runs this kernel, two launches a step, plus one
+        # statistics reset and read-back: its average duration from the
+        # events around that region
+        avg_s = st["event_seconds"] / (2 * args.steps)
     achieved = per_launch_flops / avg_s / 1e12
     roofline = {
         "bound": "alu",
