@@ -165,16 +165,14 @@ int validate(const grim_config_t* g, std::string& why)
 bool fused_rhs(const grim_ctx* c) { return c->cfg.metric == GRIM_MINKOWSKI; }
 
 // Whether a fused stage runs as the one tiled kernel (fluxes in LDS): 1- and
-// 2-D grids with the FP64 Jacobian (the FP32 form's FP64 retry pass reads
-// the fluxes from global memory), when the tiles fit the device in one
-// round (one 256-thread tile per CU).  Measured on the 2-D EMHD workload:
+// 2-D grids, when the tiles fit the device in one round (one 256-thread tile
+// per CU).  Measured on the 2-D EMHD workload:
 // 28 us per stage against 33 us for the flux and Newton kernels at 256^2
 // (256 tiles), but 110 against 103 us at 512^2 (1024 tiles), where each CU
 // runs four tiles one after another.
 bool tiled_stage(const grim_ctx* c)
 {
-    return fused_rhs(c) && c->cfg.ndim <= 2 && c->cfg.jac_precision == GRIM_JAC_F64 &&
-           grim::stage_tiles(c->L) <= (long)c->cus;
+    return fused_rhs(c) && c->cfg.ndim <= 2 && grim::stage_tiles(c->L) <= (long)c->cus;
 }
 
 StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)

@@ -165,9 +165,10 @@ struct NewtonArgs {
     // the face fluxes (fused), instead of reading what the rhs kernel stored
     // (Minkowski only; ignored for Kerr)
     int fused;
-    // with fused, 1- and 2-D, FP64 Jacobian and no network: one kernel per
-    // stage that computes a tile's face fluxes into LDS, then solves its
-    // zones (the flux kernel is not launched)
+    // with fused, 1- and 2-D and no network: one kernel per stage that
+    // computes a tile's face fluxes into LDS, then solves its zones (the flux
+    // kernel is not launched; FP32-Jacobian failures are retried in FP64 in
+    // the same lane)
     int tiled;
 };
 constexpr uint8_t kFlagRetry = 32;

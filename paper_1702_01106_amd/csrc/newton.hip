@@ -569,7 +569,7 @@ struct SrcTile {
     __device__ __forceinline__ double Pn(int v, long) const { return pn[v]; }
 };
 
-template <int NV, int ND>
+template <int NV, int ND, typename JT>
 __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
 {
     using T = Tile<ND>;
@@ -663,21 +663,41 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
         const SrcTile<NV, ND> in{pe, fx, fy, pn, lx, ly};
         ZoneSolve<NV, GeoMink> s;
         zs_begin<NV, GeoMink, ND>(a, z, a.guess, nullptr, s, &in);
-        while (!zs_step<NV, GeoMink, double>(a, s)) {
+        while (!zs_step<NV, GeoMink, JT>(a, s)) {
+        }
+        bool retried = false;
+        if constexpr (!__is_same(JT, double)) {
+            // a failed FP32-Jacobian solve is solved again from P_n with the
+            // FP64 Jacobian in the same lane (the two-pass kernels do this in
+            // a second launch); iterations and residual calls of both count
+            if (s.fl & (1 | 4 | 16)) {
+                const int it = s.iters, nc = s.ncalls;
+                zs_begin<NV, GeoMink, ND>(a, z, nullptr, nullptr, s, &in);
+                while (!zs_step<NV, GeoMink, double>(a, s)) {
+                }
+                s.iters += it;
+                s.ncalls += nc;
+                s.fl |= kFlagRetry;
+                retried = true;
+            }
         }
         zs_finish<NV, GeoMink>(a, s, false, ls);
+        ls.nrt = retried;
     }
     if (a.stats) flush_stats(a, ls);
 }
 
 template <int NV, int ND>
-hipError_t stage_tiled(const NewtonArgs& a, hipStream_t st)
+hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     using T = Tile<ND>;
     const long tiles = (long)((a.s.L.n[0] + T::TX - 1) / T::TX) * ((a.s.L.n[1] + T::TY - 1) / T::TY);
     NewtonArgs b = a;
     b.pass = 0;
-    hipLaunchKernelGGL((k_stage<NV, ND>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
+    if (jac_f32)
+        hipLaunchKernelGGL((k_stage<NV, ND, float>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
+    else
+        hipLaunchKernelGGL((k_stage<NV, ND, double>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
     return hipGetLastError();
 }
 
@@ -709,8 +729,8 @@ template <int NV, class G>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     if constexpr (G::kFlat) {
-        if (a.fused && a.tiled && !jac_f32 && !a.mlp_y && a.s.L.ndim <= 2)
-            return a.s.L.ndim == 1 ? stage_tiled<NV, 1>(a, st) : stage_tiled<NV, 2>(a, st);
+        if (a.fused && a.tiled && !a.mlp_y && a.s.L.ndim <= 2)
+            return a.s.L.ndim == 1 ? stage_tiled<NV, 1>(a, jac_f32, st) : stage_tiled<NV, 2>(a, jac_f32, st);
         if (a.fused) {
             switch (a.s.L.ndim) {
                 case 1: return newton_nd<NV, G, 1>(a, jac_f32, st);
