@@ -83,28 +83,47 @@ __device__ __forceinline__ bool lu_solve(T (&A)[N][N], T (&b)[N])
     return ok;
 }
 
-__device__ __forceinline__ unsigned long long wave_sumu64(unsigned long long x)
+// Wave-wide reductions with DPP row shifts and row broadcasts (no LDS): an
+// inclusive scan within each row of 16 lanes (shifts 1, 2, 4, 8), then row 0's
+// total into row 1 and row 2's into row 3 (broadcast of lane 15), then the
+// first two rows' total into rows 2 and 3 (broadcast of lane 31); lane 63
+// ends with the whole wave.  Lanes a DPP move cannot source get the
+// identity.  Inactive lanes must hold the identity too.
+template <int Ctrl, int RowMask = 0xf>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long x, unsigned long long id)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)id, (int)(unsigned)x, Ctrl, RowMask, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(id >> 32), (int)(unsigned)(x >> 32), Ctrl, RowMask, 0xf, false);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int wave_max(int x)
+template <class Op>
+__device__ __forceinline__ unsigned long long wave_reduce64(unsigned long long x, unsigned long long id, Op op)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
-    return x;
+    x = op(x, dpp64<0x111>(x, id));        // row_shr:1
+    x = op(x, dpp64<0x112>(x, id));        // row_shr:2
+    x = op(x, dpp64<0x114>(x, id));        // row_shr:4
+    x = op(x, dpp64<0x118>(x, id));        // row_shr:8
+    x = op(x, dpp64<0x142, 0xa>(x, id));   // row_bcast:15 into rows 1, 3
+    x = op(x, dpp64<0x143, 0xc>(x, id));   // row_bcast:31 into rows 2, 3
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, 63), hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_sumu64(unsigned long long x)
+{
+    return wave_reduce64(x, 0ull, [](unsigned long long a, unsigned long long b) { return a + b; });
 }
 
 __device__ __forceinline__ unsigned long long wave_maxu64(unsigned long long x)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        const unsigned long long y = __shfl_xor(x, o, kWave);
-        x = y > x ? y : x;
-    }
-    return x;
+    return wave_reduce64(x, 0ull, [](unsigned long long a, unsigned long long b) { return a > b ? a : b; });
+}
+
+__device__ __forceinline__ int wave_max(int x)
+{
+    return (int)wave_maxu64((unsigned long long)(unsigned)(x > 0 ? x : 0));
 }
 
 // Candidate guess from the network output y: rho, u relative to P_n,
