@@ -51,6 +51,17 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// Block order of the Kerr flux kernel, which reads 2-D (i, j) face metric
+// tables shared by every plane k: block b covers the points
+// [chunk * width, chunk * width + width) of plane k, with k = b % planes and
+// chunk = b / planes, so consecutive blocks take the same points in
+// successive planes and the blocks in flight share the tables of a few rows,
+// instead of every plane fetching the whole plane's tables again.
+__host__ __device__ inline unsigned plane_blocks(long points, unsigned planes, unsigned width)
+{
+    return (unsigned)((points + width - 1) / width) * planes;
+}
+
 // Device-side accumulators of the solver statistics.  kStatCopies copies,
 // one 128-byte line each: a wave adds into copy (block index mod copies), so
 // no address sees more than 1/kStatCopies of the waves' atomics (atomics to

@@ -89,17 +89,33 @@ struct FaceRanges {
 template <int NV, class G>
 __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
 {
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    // Minkowski: each XCD takes a contiguous eighth of the faces.  Kerr:
+    // plane-interleaved order (plane_blocks) without the XCD renumbering, so
+    // the blocks in flight on the whole device share the 2-D face metric
+    // tables of a few rows (2.8x faster than either other order on the
+    // 128x128x64 and 192x192x96 tori)
+    const unsigned b = G::kFlat ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int d = b < r.first[1] ? 0 : (b < r.first[2] ? 1 : 2);
-    // face counts per direction stay below 2^32 (the host limits zones to 2e9)
-    const unsigned t = (b - r.first[d]) * kBlock + threadIdx.x;
     const unsigned* cnt = r.cnt[d];
     const int* lo = r.lo[d];
-    if (t >= cnt[0] * cnt[1] * cnt[2]) return;
-    const unsigned q = t / cnt[0], kk = q / cnt[1];
-    const int i = lo[0] + (int)(t - q * cnt[0]);
-    const int j = lo[1] + (int)(q - kk * cnt[1]);
-    const int k = lo[2] + (int)kk;
+    int i, j, k;
+    if constexpr (G::kFlat) {
+        // face counts per direction stay below 2^32 (the host limits zones to 2e9)
+        const unsigned t = (b - r.first[d]) * kBlock + threadIdx.x;
+        if (t >= cnt[0] * cnt[1] * cnt[2]) return;
+        const unsigned q = t / cnt[0], kk = q / cnt[1];
+        i = lo[0] + (int)(t - q * cnt[0]);
+        j = lo[1] + (int)(q - kk * cnt[1]);
+        k = lo[2] + (int)kk;
+    } else {
+        const unsigned bb = b - r.first[d], kk = bb % cnt[2];
+        const unsigned t = (bb / cnt[2]) * kBlock + threadIdx.x;
+        if (t >= cnt[0] * cnt[1]) return;
+        const unsigned q = t / cnt[0];
+        i = lo[0] + (int)(t - q * cnt[0]);
+        j = lo[1] + (int)q;
+        k = lo[2] + (int)kk;
+    }
     if (d == 0) face_flux<NV, G, 1>(a, i, j, k);
     else if (d == 1) face_flux<NV, G, 2>(a, i, j, k);
     else face_flux<NV, G, 3>(a, i, j, k);
@@ -108,10 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
 // One thread per interior zone: the stage right-hand side (zone_rhs), stored
 // for the Newton kernel.
 template <int NV, class G, int ND>
-__global__ __launch_bounds__(kBlock) void k_rhs(StageArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_rhs(StageArgs a)
 {
-    // plain block order: with the XCD renumbering the Kerr launches, which
-    // read the 2-D metric and connection tables of every plane, ran 5-20% slower
+    // plain block order: the plane-interleaved order that speeds up the Kerr
+    // flux kernel made this one 16% slower on the 128x128x64 torus (5% faster
+    // on the 192x192x96 one), and the XCD renumbering 5-20% slower
     const long z = (long)blockIdx.x * kBlock + threadIdx.x;
     if (z >= a.L.nz) return;
     double rhs[NV], co[kEmhdCoef];
@@ -268,7 +285,8 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
             else if (e < nd) { r.lo[d][e] = L.g[e] - 1; r.cnt[d][e] = L.n[e] + 2; }
             else { r.lo[d][e] = 0; r.cnt[d][e] = 1; }
         }
-        blocks += nblocks((long)r.cnt[d][0] * r.cnt[d][1] * r.cnt[d][2]);
+        blocks += G::kFlat ? nblocks((long)r.cnt[d][0] * r.cnt[d][1] * r.cnt[d][2])
+                           : plane_blocks((long)r.cnt[d][0] * r.cnt[d][1], r.cnt[d][2], kBlock);
     }
     r.first[3] = blocks;
     for (int d = nd; d < 3; ++d) r.first[d] = blocks;

@@ -526,9 +526,11 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
 template <int NV, class G, typename JT, int ND>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
+    // (the plane-interleaved order of the Kerr flux kernel made this one
+    // 4-6% slower on the Kerr tori)
     const long z = (long)xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x;
-    const bool retry = a.pass == 2;
     bool active = z < a.s.L.nz;
+    const bool retry = a.pass == 2;
     if (retry) {
         active = active && (a.flags[z] & kFlagRetry);
         if (__ballot(active) == 0ull) return;  // wave-uniform exit
