@@ -59,6 +59,13 @@ struct SrcGlobal {
         return a.PE[(long)v * a.L.cells + at(m, o1, o2, o3)];
     }
     __device__ __forceinline__ double Pn(int v, long m) const { return a.Pn[(long)v * a.L.cells + m]; }
+    // Kerr: the centre metric and connection of table point p = j N1 + i
+    template <class G>
+    __device__ __forceinline__ void centre(G& g, size_t p) const
+    {
+        if constexpr (!G::kFlat) load_geo(g, a.geo.centre, p, a.geo.stride);
+    }
+    __device__ __forceinline__ double conn(int q, size_t p) const { return a.geo.conn[(size_t)q * a.geo.stride + p]; }
 };
 
 // Flux-CT (Sec. 4.2): the edge EMF as the average of the four face B-fluxes
@@ -160,7 +167,7 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         divF[v] = s;
     }
 
-    if constexpr (!G::kFlat) load_geo(g, a.geo.centre, (size_t)((long)j * L.N[0] + i), a.geo.stride);
+    if constexpr (!G::kFlat) in.centre(g, (size_t)((long)j * L.N[0] + i));
     const double idt = 1.0 / a.dtp;
     double Pn[NV], PE[NV];
 #pragma unroll
@@ -196,7 +203,7 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         for (int l = 0; l < 4; ++l) {
             double c[4][4];  // Gamma^l_{a b}
 #pragma unroll
-            for (int q = 0; q < 16; ++q) c[q / 4][q % 4] = a.geo.conn[(size_t)(l * 16 + q) * a.geo.stride + p];
+            for (int q = 0; q < 16; ++q) c[q / 4][q % 4] = in.conn(l * 16 + q, p);
 #pragma unroll
             for (int n = 0; n < 4; ++n)
 #pragma unroll
