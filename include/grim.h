@@ -255,6 +255,12 @@ int grim_collect_pairs(grim_ctx_t* ctx, double dt, int nsteps, int stride, float
  * Sec. 7.2).  a, b, c device pointers.  Enqueued, not timed. */
 int grim_stream_add(grim_ctx_t* ctx, const double* a, const double* b, double* c, size_t n);
 
+/* Test hook for the arithmetic of the hot loops: for each x[i] (device, n
+ * doubles) writes the library's reciprocal, inverse square root and square
+ * root (the hardware estimates refined by two Newton-Raphson steps) to
+ * out[3i], out[3i + 1], out[3i + 2] (device).  Synchronises. */
+int grim_math_probe(grim_ctx_t* ctx, const double* x, double* out, size_t n);
+
 #ifdef __cplusplus
 }
 #endif

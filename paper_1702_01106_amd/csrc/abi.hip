@@ -833,6 +833,15 @@ int grim_collect_pairs(grim_ctx_t* c, double dt, int nsteps, int stride, float* 
     return GRIM_OK;
 }
 
+int grim_math_probe(grim_ctx_t* c, const double* x, double* out, size_t n)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (n > 0 && (!x || !out)) return fail(c, GRIM_E_INVALID_ARG, "null pointer");
+    HIP_TRY(c, grim::launch_math_probe(x, out, n, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
 int grim_stream_add(grim_ctx_t* c, const double* a, const double* b, double* cc, size_t n)
 {
     if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");

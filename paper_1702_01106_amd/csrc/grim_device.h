@@ -59,10 +59,14 @@ __device__ __forceinline__ double rsq_nr(double x)
 }
 
 // sqrt(x) = x / sqrt(x), exact 0 for x = 0 (the clamp turns 0 * inf into
-// 0 * DBL_MAX).  A negative argument gives -inf or NaN rather than exactly
-// NaN; every caller only tests finiteness.  (A select on x == 0 instead of
-// the clamp costs the stage kernels 30-90 registers.)
-__device__ __forceinline__ double sqrt_nr(double x) { return x * fmin(rsq_nr(x), 1.7976931348623157e308); }
+// 0 * DBL_MAX) and NaN for x < 0 (the clamp lets NaN through, which fmin
+// would not); +inf gives NaN.  (A select on x == 0 instead costs the stage
+// kernels 30-90 registers.)
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = rsq_nr(x);
+    return x * (y > 1.7976931348623157e308 ? 1.7976931348623157e308 : y);
+}
 
 // Physical constants shared by every kernel of one context.
 struct Phys {

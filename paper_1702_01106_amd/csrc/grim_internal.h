@@ -198,6 +198,7 @@ hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int
                       unsigned long long* out_bits, hipStream_t st);
 hipError_t launch_zero_stats(DevStats* s, hipStream_t st);
 hipError_t launch_stream_add(const double* a, const double* b, double* c, size_t n, hipStream_t st);
+hipError_t launch_math_probe(const double* x, double* out, size_t n, hipStream_t st);
 hipError_t launch_copy_interior(const Layout& L, int nvar, const double* src, int src_ghosted, double* dst,
                                 int dst_ghosted, hipStream_t st);
 hipError_t launch_collect(const StageArgs& a, int nvar, const double* Pout, int out_ghosted, int stride, int phase,

@@ -143,6 +143,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) 
     }
 }
 
+// ------------------------------------------------------------------ math hook
+
+__global__ __launch_bounds__(kBlock) void k_math_probe(const double* x, double* out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double v = x[i];
+    out[3 * i] = rcp_nr(v);
+    out[3 * i + 1] = rsq_nr(v);
+    out[3 * i + 2] = sqrt_nr(v);
+}
+
 // ------------------------------------------------------------------ residual hook
 
 template <int NV, class G>
@@ -369,6 +381,13 @@ hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int
 hipError_t launch_zero_stats(DevStats* s, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero_stats, dim3(kStatCopies), dim3(64), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_math_probe(const double* x, double* out, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_math_probe, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, x, out, n);
     return hipGetLastError();
 }
 

@@ -103,6 +103,7 @@ def load():
     L.grim_explicit.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.grim_get_zone_results.argtypes = [_VP, _VP, _VP, C.c_int]
     L.grim_stream_add.argtypes = [_VP, _VP, _VP, _VP, C.c_size_t]
+    L.grim_math_probe.argtypes = [_VP, _VP, _VP, C.c_size_t]
     L.grim_profile.argtypes = [_VP, C.c_int]
     L.grim_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.grim_mlp_set_weights.argtypes = [_VP, _VP, C.c_size_t]
@@ -118,7 +119,7 @@ def load():
 def exported_symbols():
     return ["grim_create", "grim_destroy", "grim_last_error", "grim_last_global_error", "grim_device_bytes",
             "grim_set_prims", "grim_get_prims", "grim_cfl_dt", "grim_run", "grim_residual", "grim_stage_solve",
-            "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_profile", "grim_kernel_times",
+            "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_math_probe", "grim_profile", "grim_kernel_times",
             "grim_mlp_set_weights", "grim_mlp_get_weights", "grim_mlp_forward", "grim_mlp_backward",
             "grim_mlp_train", "grim_collect_pairs"]
 
@@ -224,6 +225,10 @@ def grim_explicit(ctx, PE, divF, srcE, emhd_sp=None):
 
 def grim_get_zone_results(ctx, flags, iters, on_device):
     _check(ctx, load().grim_get_zone_results(ctx, _ptr(flags), _ptr(iters), int(on_device)), "grim_get_zone_results")
+
+
+def grim_math_probe(ctx, x, out, n):
+    _check(ctx, load().grim_math_probe(ctx, _ptr(x), _ptr(out), int(n)), "grim_math_probe")
 
 
 def grim_stream_add(ctx, a, b, c, n):
