@@ -32,7 +32,6 @@ struct grim_ctx {
     double* H = nullptr;                // ghosted half-step state P_{n+1/2}
     int cur = 0;                         // buffer holding the current state
     double* F[3] = {nullptr, nullptr, nullptr};
-    double* E[3] = {nullptr, nullptr, nullptr};
     double* rhs = nullptr;
     double* coef = nullptr;
     double* interior = nullptr;          // staging buffer, interior layout
@@ -120,7 +119,7 @@ void release(grim_ctx* c)
         if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->own_st && c->st) hipStreamDestroy(c->st);
-    void* ptrs[] = {c->P[0], c->P[1], c->H, c->F[0], c->F[1], c->F[2], c->E[0], c->E[1], c->E[2], c->rhs, c->coef,
+    void* ptrs[] = {c->P[0], c->P[1], c->H, c->F[0], c->F[1], c->F[2], c->rhs, c->coef,
                     c->interior, c->hookP[0], c->hookP[1], c->iters, c->resid, c->flags, c->stats, c->u64,
                     c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn, c->mlp_p,
                     c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->mlp_x, c->mlp_y, c->mlp_grad, c->adam_m, c->adam_v,
@@ -186,10 +185,7 @@ StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp
     a.geo.stride = (size_t)c->L.N[0] * c->L.N[1];
     a.Pn = Pn;
     a.PE = PE;
-    for (int d = 0; d < 3; ++d) {
-        a.F[d] = c->F[d];
-        a.E[d] = c->E[d];
-    }
+    for (int d = 0; d < 3; ++d) a.F[d] = c->F[d];
     a.rhs = c->rhs;
     a.coef = c->coef;
     a.dtp = dtp;
@@ -448,9 +444,6 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     for (int i = 0; i < 2 && !rc; ++i) rc = dalloc(c, &c->P[i], nv * L.cells);
     if (!rc) rc = dalloc(c, &c->H, nv * L.cells);
     for (int d = 0; d < cfg->ndim && !rc; ++d) rc = dalloc(c, &c->F[d], nv * L.cells);
-    if (cfg->ndim >= 2)
-        for (int d = 0; d < 3 && !rc; ++d)
-            if (cfg->ndim == 3 || d == 2) rc = dalloc(c, &c->E[d], (size_t)L.cells);
     if (!rc) rc = dalloc(c, &c->rhs, nv * L.nz);
     if (!rc && c->nvar == GRIM_EMHD) rc = dalloc(c, &c->coef, (size_t)grim::kEmhdCoef * L.nz);
     if (!rc) rc = dalloc(c, &c->interior, nv * L.nz);
@@ -481,7 +474,6 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     if (e == hipSuccess) e = hipMemsetAsync(c->H, 0, sizeof(double) * nv * L.cells, c->st);
     for (int d = 0; d < 3 && e == hipSuccess; ++d) {
         if (c->F[d]) e = hipMemsetAsync(c->F[d], 0, sizeof(double) * nv * L.cells, c->st);
-        if (e == hipSuccess && c->E[d]) e = hipMemsetAsync(c->E[d], 0, sizeof(double) * L.cells, c->st);
     }
     if (e == hipSuccess && cfg->metric == GRIM_MKS_KERR)
         e = grim::build_geometry(L, cfg->spin_a, cfg->mks_h, c->geo_centre, c->geo_face, c->geo_conn, c->st);

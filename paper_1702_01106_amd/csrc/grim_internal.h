@@ -138,7 +138,6 @@ struct StageArgs {
     const double* Pn;   // ghosted P_n
     const double* PE;   // ghosted P^E (ghosts filled)
     double* F[3];       // face fluxes per active direction, ghosted layout
-    double* E[3];       // edge EMFs E1, E2, E3 (flux-CT), ghosted layout
     double* rhs;        // [nvar][nz]
     double* coef;       // [kEmhdCoef][nz] (EMHD)
     double dtp;
