@@ -86,6 +86,8 @@ def _within_spread(err, spread, floor):
 CASES = {
     # name: (workload dict, initial state)
     "srmhd1d": lambda: (W.workload("srmhd1d_alfven_128"), None),
+    # two 256-zone tiles of the one-kernel stage, the second ragged
+    "srmhd1d_300": lambda: (W.small("srmhd1d_alfven_128", [300]), None),
     "emhd2d_ragged": lambda: (W.small("emhd2d_modes_256", [70, 45]), None),
     "ideal2d": lambda: (dict(W.small("emhd2d_modes_256", [33, 20]), nvar=8), None),
     "ideal3d": lambda: (dict(W._BASE, ndim=3, n=[20, 12, 9], x_start=[0, 0, 0], x_end=[1, 1, 1], nvar=8,
@@ -100,7 +102,7 @@ KERR = ("kerr_ideal", "kerr_emhd")
 
 def _state(name, wl):
     rng = np.random.default_rng(sum(map(ord, name)))
-    if name == "srmhd1d":
+    if name.startswith("srmhd1d"):
         return W.alfven_1d(wl, seed=3)
     if name in KERR:
         return W.kerr_torus(wl, seed=2)
@@ -232,16 +234,24 @@ def test_stage_solve(torch_cuda, oracle_mod, name, jac):
     assert err.max() < 1e-6, err.max()
     if jac == "f64":
         assert err.max() < 1e-8, err.max()
-        assert np.mean(git == it) > 0.98
+        # a zone whose residual lands on the tolerance stops one iteration
+        # earlier or later under rounding-level changes of its input; the
+        # oracle's own agreement under 1e-14 perturbations (worst of three
+        # draws) bounds how many such zones may differ, by one iteration
+        same = min(_oracle_spread(lambda Q: o.stage(Q, PE, dtp)[:2], Pn, rel=1e-14, seed=sd, base=(ref, it))[1]
+                   for sd in (11, 12, 13))
+        _say(f"  same-iters {np.mean(git == it):.3f}, oracle under perturbation {same:.3f}")
+        assert np.mean(git == it) >= min(0.98, same - 0.02), (np.mean(git == it), same)
+        assert np.abs(git.astype(int) - it).max() <= 1
 
 
-@pytest.mark.parametrize("name", ["srmhd1d", "emhd2d_ragged", "ideal3d", "kerr_ideal", "kerr_emhd"])
+@pytest.mark.parametrize("name", ["srmhd1d", "srmhd1d_300", "emhd2d_ragged", "ideal3d", "kerr_ideal", "kerr_emhd"])
 def test_steps(torch_cuda, oracle_mod, name):
     wl, _ = CASES[name]()
     P0 = _state(name, wl)
     o = oracle_mod.Oracle(wl)
     dt = o.cfl_dt(P0, 0.5)
-    nsteps = 10 if name == "srmhd1d" else 3
+    nsteps = 10 if name.startswith("srmhd1d") else 3
     _say(f"steps {name} x{nsteps}")
     ref, st = o.step(P0, dt, nsteps)
     g = _ctx(wl)
