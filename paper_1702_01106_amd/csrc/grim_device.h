@@ -163,7 +163,12 @@ struct St {
 // ut^i ut^j), u^0 = gamma/alpha, u^i = ut^i - gamma alpha g^{0i};
 // b^0 = B^i u_i, b^i = (B^i + b^0 u^i)/u^0; P = (gamma-1) u; bhat = b/|b|
 // (zero for b^2 < 1e-30).
-template <int NV, class G>
+// kSelect: 1/|b| is computed unconditionally and selected, which keeps the
+// caller's code in one basic block (the Minkowski kernels and every residual
+// evaluation gain from it); otherwise a branch skips it where a whole wave
+// has b^2 = 0 (field-free Kerr atmosphere), which the Kerr explicit-stage
+// kernels gain from.
+template <int NV, class G, bool kSelect = G::kFlat>
 __device__ __forceinline__ void derive(const double* P, const G& g, const Phys& ph, St<NV>& s)
 {
     double q2 = 0.0;
@@ -202,8 +207,13 @@ __device__ __forceinline__ void derive(const double* P, const G& g, const Phys& 
     s.bsq = s.bcon[0] * s.bcov[0] + s.bcon[1] * s.bcov[1] + s.bcon[2] * s.bcov[2] + s.bcon[3] * s.bcov[3];
     s.pg = ph.gm1 * P[UU];
     if constexpr (NV == 10) {
-        const bool has = s.bsq > 1e-30;
-        const double ib = has ? rsq_nr(s.bsq) : 0.0;
+        double ib;
+        if constexpr (kSelect) {
+            const double r = rsq_nr(s.bsq);
+            ib = s.bsq > 1e-30 ? r : 0.0;
+        } else {
+            ib = s.bsq > 1e-30 ? rsq_nr(s.bsq) : 0.0;
+        }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             s.bh[m] = s.bcon[m] * ib;

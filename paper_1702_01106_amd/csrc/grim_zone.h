@@ -87,7 +87,7 @@ template <int NV, class G>
 __device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G>& zc, const Phys& ph, double* R)
 {
     St<NV> s;
-    derive<NV>(P, zc.g, ph, s);
+    derive<NV, G, true>(P, zc.g, ph, s);
     double T[4];
     trow<NV, 0>(P, s, T);
     const double gd = zc.g.gdet();

@@ -627,54 +627,77 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
             const int q = tid + r * T::kThreads;
             const int v = q / (T::PY * T::PX), rr = (q / T::PX) % T::PY, c = q % T::PX;
             const int gi = gi0 + c, gj = gj0 + rr;
-            b[r] = (q < n && gi < L.N[0] && gj < L.N[1]) ? a.s.PE[(long)v * C + L.cell(gi, gj, 0)] : 0.0;
+            // a cell outside reads element 0 instead and is multiplied by
+            // zero (a select would let the compiler put a branch around the
+            // load)
+            const bool in = q < n && gi < L.N[0] && gj < L.N[1];
+            b[r] = a.s.PE[in ? (long)v * C + L.cell(gi, gj, 0) : 0L] * (in ? 1.0 : 0.0);
         }
 #pragma unroll
         for (int r = 0; r < per; ++r)
-            if (tid + r * T::kThreads < n) pe[tid + r * T::kThreads] = b[r];
+            if (r < per - 1 || tid + r * T::kThreads < n) pe[tid + r * T::kThreads] = b[r];
     }
     __syncthreads();
 
     // the tile's face fluxes.  First every thread computes x-face t and
-    // y-face t together, unconditionally (indices clamped into the tile, so a
-    // face not needed reads defined LDS and is simply not stored): two
-    // independent chains per lane in one basic block.  The remaining faces
-    // go to waves 0-1 (x) and 2-3 (y), so no wave computes more than three.
+    // y-face t together: two independent chains per lane in one basic block,
+    // both stored unconditionally after both are computed (a conditional
+    // store would let the compiler sink each chain into its own branch).  In
+    // a ragged tile a face past the tile's zones reads defined LDS (zeros
+    // past the grid) and lands in a slot that no zone reads.  The remaining
+    // faces go to waves 0-1 (x) and 2-3 (y), so no wave computes more than
+    // three.
     constexpr int nxf = T::XX * T::XY, nyf = T::YX * T::YY;
+    static_assert(nxf >= T::kThreads && (ND == 1 || nyf >= T::kThreads), "every thread has a first face");
     static_assert(nxf - T::kThreads <= T::kThreads / 2 && nyf - T::kThreads <= T::kThreads / 2, "face split");
     const Phys& ph = a.s.ph;
     const GeoMink g{};
-    auto xface = [&](int q, bool keep) {
+    auto xface = [&](int q, double* f) {
         const int cx = q % T::XX, cy = q / T::XX - T::XR;
         const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
-        double f[NV];
         llf_face<NV, GeoMink, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, f);
-        if (keep && cx <= w && cy <= (ND == 1 ? 0 : h)) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) fx[(v * T::XY + cy + T::XR) * T::XX + cx] = f[v];
-        }
     };
-    auto yface = [&](int q, bool keep) {
+    auto xstore = [&](int q, const double* f) {
+        const int cx = q % T::XX, cy = q / T::XX - T::XR;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fx[(v * T::XY + cy + T::XR) * T::XX + cx] = f[v];
+    };
+    auto yface = [&](int q, double* f) {
         const int ex = q % T::YX - 1, ey = q / T::YX;
         const double* p = pe + (ey + T::HY) * T::PX + ex + 2;
-        double f[NV];
         llf_face<NV, GeoMink, 2>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o * T::PX]; }, f);
-        if (keep && ex <= w && ey <= h) {
+    };
+    auto ystore = [&](int q, const double* f) {
+        const int ex = q % T::YX - 1, ey = q / T::YX;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = f[v];
-        }
+        for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = f[v];
     };
     if constexpr (ND >= 2) {
-        xface(min(tid, nxf - 1), tid < nxf);
-        yface(min(tid, nyf - 1), tid < nyf);
+        {
+            double f0[NV], f1[NV];
+            xface(tid, f0);
+            yface(tid, f1);
+            xstore(tid, f0);
+            ystore(tid, f1);
+        }
+        double f2[NV];
         if (tid < T::kThreads / 2) {
-            if (tid < nxf - T::kThreads) xface(T::kThreads + tid, true);
+            if (tid < nxf - T::kThreads) {
+                xface(T::kThreads + tid, f2);
+                xstore(T::kThreads + tid, f2);
+            }
         } else if (tid - T::kThreads / 2 < nyf - T::kThreads) {
-            yface(tid - T::kThreads / 2 + T::kThreads, true);
+            yface(tid - T::kThreads / 2 + T::kThreads, f2);
+            ystore(tid - T::kThreads / 2 + T::kThreads, f2);
         }
     } else {
-        xface(tid, true);
-        if (tid < nxf - T::kThreads) xface(T::kThreads + tid, true);
+        double f0[NV];
+        xface(tid, f0);
+        xstore(tid, f0);
+        if (tid < nxf - T::kThreads) {
+            xface(T::kThreads + tid, f0);
+            xstore(T::kThreads + tid, f0);
+        }
     }
     __syncthreads();
 
