@@ -145,8 +145,13 @@ __device__ __forceinline__ void Pc_from_net(const double* pn, const float* y, do
 
 // The Newton direction dP (zero in the B entries) at P, whose residual is R:
 // the finite-difference Jacobian over the system's unknowns, column by
-// column, then LU with partial pivoting.  Returns false on an exactly zero
-// pivot.
+// column, then LU with partial pivoting.  The energy row of the linear
+// system is taken as energy + mass (both sides), which removes the rest-mass
+// energy from it: an elementary row operation, so dP is unchanged, but the
+// mass row's rho entry (u^0) no longer competes with the energy row's
+// (about -(u^0)^2) for the first pivot, a near tie that made partial
+// pivoting swap the two rows in about 40% of slow-flow zones.  Returns false
+// on an exactly zero pivot.
 template <int NV, class G, typename JT>
 __device__ __forceinline__ bool newton_dir(const double* P, const double* R, const ZoneC<NV, G>& zc,
                                            const Phys& ph, double eps, double* dP)
@@ -173,11 +178,15 @@ __device__ __forceinline__ bool newton_dir(const double* P, const double* R, con
         zone_residual<NV, G>(Pe, zc, ph, Re);
         const double ih = rcp_nr(h);
 #pragma unroll
-        for (int i = 0; i < N; ++i) J[i][j] = (JT)((Re[unk(i)] - R[unk(i)]) * ih);
+        for (int i = 0; i < N; ++i) {
+            const double d = Re[unk(i)] - R[unk(i)];
+            J[i][j] = (JT)((i == 1 ? d + (Re[RHO] - R[RHO]) : d) * ih);
+        }
     }
+    static_assert(unk(0) == RHO && unk(1) == UU, "mass and energy rows come first");
     JT x[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = (JT)(-R[unk(i)]);
+    for (int i = 0; i < N; ++i) x[i] = (JT)(i == 1 ? -(R[UU] + R[RHO]) : -R[unk(i)]);
     if (!lu_solve<N, JT>(J, x)) return false;
 #pragma unroll
     for (int i = 0; i < N; ++i) dP[unk(i)] = (double)x[i];
