@@ -566,6 +566,51 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 // Fluxes never go to global memory and the stage is one launch; the price is
 // recomputing the faces shared with neighbouring tiles (2.4 faces per zone in
 // 2-D against 2.0).
+// Exchange a double with the other lane of its pair (lanes 2m and 2m + 1):
+// DPP quad permutation [1, 0, 3, 2].  Every lane of the wave must be active.
+__device__ __forceinline__ double pair_swap(double x)
+{
+    constexpr int kSwapPairs = 0xb1;
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, kSwapPairs, 0xf, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), kSwapPairs, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The LLF flux of one face normal to DIR computed by a pair of lanes (Sec.
+// 2.4): the even lane builds the left state and the odd lane the right one
+// (PLM, derived state, wave speed, U and F, each exactly as llf_face builds
+// it), the pair swaps c_max, U and F, and the even lane combines them in
+// llf_face's order; the odd lane's f is not meaningful.  cell(v, o) is as
+// for llf_face.  Every lane of the wave must take part (the swaps are
+// cross-lane).
+template <int NV, int DIR, class Cell>
+__device__ __forceinline__ void llf_pair(const Phys& ph, const GeoMink& g, const Cell& cell, bool right, double* f)
+{
+    const double th = ph.theta;
+    const int o = right ? -1 : -2;
+    double P[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double x0 = cell(v, o), x1 = cell(v, o + 1), x2 = cell(v, o + 2);
+        const double h = 0.5 * gmm(x1 - x0, x2 - x1, th);
+        P[v] = right ? x1 - h : x1 + h;
+    }
+    St<NV> st;
+    derive<NV>(P, g, ph, st);
+    const double c = cmax<NV, DIR>(P, g, st, ph);
+    double U[NV], F[NV];
+    conserved<NV>(P, g, st, ph, U);
+    flux<NV, DIR>(P, g, st, ph, F);
+    const double cc = fmax(c, pair_swap(c));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
+        f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (F[v] + Fo) - 0.5 * cc * (Uo - U[v]);
+    }
+}
+
 template <int ND>
 struct Tile {
     static constexpr int TX = ND == 1 ? 256 : 16, TY = ND == 1 ? 1 : 16;
@@ -654,11 +699,11 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
     // store would let the compiler sink each chain into its own branch).  In
     // a ragged tile a face past the tile's zones reads defined LDS (zeros
     // past the grid) and lands in a slot that no zone reads.  The remaining
-    // faces go to waves 0-1 (x) and 2-3 (y), so no wave computes more than
-    // three.
+    // faces (100 of 612 in 2-D) are then computed by lane pairs, so every
+    // wave's third round is half a face's chain instead of two waves doing
+    // a whole face while the other two wait at the barrier.
     constexpr int nxf = T::XX * T::XY, nyf = T::YX * T::YY;
     static_assert(nxf >= T::kThreads && (ND == 1 || nyf >= T::kThreads), "every thread has a first face");
-    static_assert(nxf - T::kThreads <= T::kThreads / 2 && nyf - T::kThreads <= T::kThreads / 2, "face split");
     const Phys& ph = a.s.ph;
     const GeoMink g{};
     auto xface = [&](int q, double* f) {
@@ -689,15 +734,27 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
             xstore(tid, f0);
             ystore(tid, f1);
         }
+        // the remaining faces, each by a pair of lanes (half a face's chain
+        // per lane): waves 0-1 take the x-faces and waves 2-3 the y-faces, a
+        // wave-uniform choice; lanes past the last face repeat it and do
+        // not store
+        static_assert(2 * (nxf - T::kThreads) <= T::kThreads / 2 && 2 * (nyf - T::kThreads) <= T::kThreads / 2,
+                      "pair split");
+        const int e = tid & (T::kThreads / 2 - 1);
+        const bool right = (e & 1) != 0;
         double f2[NV];
         if (tid < T::kThreads / 2) {
-            if (tid < nxf - T::kThreads) {
-                xface(T::kThreads + tid, f2);
-                xstore(T::kThreads + tid, f2);
-            }
-        } else if (tid - T::kThreads / 2 < nyf - T::kThreads) {
-            yface(tid - T::kThreads / 2 + T::kThreads, f2);
-            ystore(tid - T::kThreads / 2 + T::kThreads, f2);
+            const int q = T::kThreads + min(e >> 1, nxf - T::kThreads - 1);
+            const int cx = q % T::XX, cy = q / T::XX - T::XR;
+            const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
+            llf_pair<NV, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, right, f2);
+            if (!right && (e >> 1) < nxf - T::kThreads) xstore(q, f2);
+        } else {
+            const int q = T::kThreads + min(e >> 1, nyf - T::kThreads - 1);
+            const int ex = q % T::YX - 1, ey = q / T::YX;
+            const double* p = pe + (ey + T::HY) * T::PX + ex + 2;
+            llf_pair<NV, 2>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o * T::PX]; }, right, f2);
+            if (!right && (e >> 1) < nyf - T::kThreads) ystore(q, f2);
         }
     } else {
         double f0[NV];

@@ -94,7 +94,11 @@ def test_learned_guess_in_the_solver(torch_cuda):
     """Pairs from FP64 runs on seeds 1-2, trained on the GPU, then seed 0: the
     learned guess cuts the mean Newton iterations and the result agrees with the
     plain solve; a network scaled by 1e3 is rejected everywhere (fallback) and
-    gives the plain result bit for bit."""
+    gives the plain result to the same bound.  (Not bit for bit: the plain
+    solve of this grid runs the one-kernel stage, the learned one the flux and
+    Newton kernels, and the two build the face fluxes in different code,
+    where the compiler may form different multiply-adds; Newton's stopping
+    test turns rounding differences into differences below the tolerance.)"""
     from paper_1702_01106_amd import grim, learned
 
     wl = W.small("emhd2d_modes_256", [128, 128])
@@ -123,4 +127,5 @@ def test_learned_guess_in_the_solver(torch_cuda):
     junk.set_prims(P0)
     st2 = junk.run(dt, 10)
     assert st2["n_fallback"] >= 0.99 * st2["zone_stages"]
-    assert np.array_equal(junk.get_prims(), ref)
+    assert st2["n_fail"] == 0 and st2["max_resid"] < wl["tol"]
+    assert prim_rel_err(junk.get_prims(), ref).max() < 1e-6
