@@ -662,34 +662,44 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
     const int lx = tid % T::TX, ly = tid / T::TX;
     const bool active = lx < w && ly < h;
     const long z = (long)(y0 + ly) * L.n[0] + x0 + lx;
-    // the zone's P_n, read now so that its latency hides behind the tile work
-    double pn[NV];
-    if (active) {
-        const long m = L.cell(x0 + lx + L.g[0], y0 + ly + L.g[1], 0);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * C + m];
-    }
-
     // P^E of the tile and its halo, every read issued before the first LDS
-    // write; cells past the ghosted grid (ragged tiles) are not needed
+    // write; cells past the ghosted grid (ragged tiles) are not needed.  A
+    // thread takes whole cells (all NV variables at one address plus a
+    // stride), so each load costs an add, not a division chain.  The zone's
+    // P_n (needed only by the solve) is read after them: loads complete in
+    // order, so the face phase waits for P^E alone and P_n arrives behind it
+    double pn[NV];
     {
         const int gi0 = x0 + L.g[0] - 2, gj0 = y0 + L.g[1] - T::HY;
-        constexpr int n = NV * T::PY * T::PX, per = (n + T::kThreads - 1) / T::kThreads;
-        double b[per];
+        constexpr int cells = T::PY * T::PX, rounds = (cells + T::kThreads - 1) / T::kThreads;
+        double b[rounds][NV];
 #pragma unroll
-        for (int r = 0; r < per; ++r) {
-            const int q = tid + r * T::kThreads;
-            const int v = q / (T::PY * T::PX), rr = (q / T::PX) % T::PY, c = q % T::PX;
-            const int gi = gi0 + c, gj = gj0 + rr;
-            // a cell outside reads element 0 instead and is multiplied by
-            // zero (a select would let the compiler put a branch around the
-            // load)
-            const bool in = q < n && gi < L.N[0] && gj < L.N[1];
-            b[r] = a.s.PE[in ? (long)v * C + L.cell(gi, gj, 0) : 0L] * (in ? 1.0 : 0.0);
+        for (int r = 0; r < rounds; ++r) {
+            // a cell outside the tile or the grid reads cell 0 instead and is
+            // multiplied by zero: no load sits in a branch, whose end would
+            // have to wait for it
+            const int cq = tid + r * T::kThreads;
+            const int gi = gi0 + cq % T::PX, gj = gj0 + cq / T::PX;
+            const bool in = cq < cells && gi < L.N[0] && gj < L.N[1];
+            const double keep = in ? 1.0 : 0.0;
+            const double* src = a.s.PE + (in ? L.cell(gi, gj, 0) : 0L);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) b[r][v] = src[(long)v * C] * keep;
+        }
+        {
+            // a lane without a zone (ragged tile) reads cell 0 and never uses it
+            const long m = active ? L.cell(x0 + lx + L.g[0], y0 + ly + L.g[1], 0) : 0L;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) pn[v] = a.s.Pn[(long)v * C + m];
         }
 #pragma unroll
-        for (int r = 0; r < per; ++r)
-            if (r < per - 1 || tid + r * T::kThreads < n) pe[tid + r * T::kThreads] = b[r];
+        for (int r = 0; r < rounds; ++r) {
+            const int cq = tid + r * T::kThreads;
+            if (r < rounds - 1 || cq < cells) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) pe[v * cells + cq] = b[r][v];
+            }
+        }
     }
     __syncthreads();
 
