@@ -62,7 +62,6 @@ struct grim_ctx {
     // from buffer p (an even count, so the step after it starts from p again)
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     double graph_dt = 0.0;
-    int cus = 0;  // compute units of the device
     bool timing = false;
     struct Mark {
         int group;
@@ -163,15 +162,14 @@ int validate(const grim_config_t* g, std::string& why)
 // Whether stage solves compute the right-hand side inside the Newton kernel.
 bool fused_rhs(const grim_ctx* c) { return c->cfg.metric == GRIM_MINKOWSKI; }
 
-// Whether a fused stage runs as the one tiled kernel (fluxes in LDS): 1- and
-// 2-D grids, when the tiles fit the device in one round (one 256-thread tile
-// per CU).  Measured on the 2-D EMHD workload:
-// 28 us per stage against 33 us for the flux and Newton kernels at 256^2
-// (256 tiles), but 110 against 103 us at 512^2 (1024 tiles), where each CU
-// runs four tiles one after another.
+// Whether a fused stage runs as the one tiled kernel (fluxes in LDS): every
+// 1- and 2-D grid.  Two tiles fit a CU (79 KiB of LDS and at most 256
+// registers each), so past 256 tiles a SIMD holds two waves.  Measured on
+// the 2-D EMHD workload: 24 us per stage against 33 us for the flux and
+// Newton kernels at 256^2, and 71 against 91 us at 512^2.
 bool tiled_stage(const grim_ctx* c)
 {
-    return fused_rhs(c) && c->cfg.ndim <= 2 && grim::stage_tiles(c->L) <= (long)c->cus;
+    return fused_rhs(c) && c->cfg.ndim <= 2;
 }
 
 StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)
@@ -406,12 +404,6 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
             delete c;
             return GRIM_E_HIP;
         }
-    }
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            c->cus = 0;
     }
     c->nvar = cfg->model;
     Layout& L = c->L;

@@ -645,7 +645,7 @@ struct SrcTile {
 };
 
 template <int NV, int ND, typename JT>
-__global__ __launch_bounds__(Tile<ND>::kThreads) void k_stage(NewtonArgs a)
+__global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(NewtonArgs a)
 {
     using T = Tile<ND>;
     __shared__ double lds[T::template words<NV>()];

@@ -367,9 +367,10 @@ def test_failure_flags_match_oracle(torch_cuda, oracle_mod):
 
 @pytest.mark.timeout(300)
 def test_fused_and_stored_rhs_agree_at_scale(torch_cuda, oracle_mod):
-    """512^2 EMHD, four waves per SIMD, so waves of one launch run at
-    different times: the Newton kernel that computes each zone's right-hand
-    side itself (the plain path) and the one that reads it from the rhs kernel
+    """512^2 EMHD, more tiles than CUs, so blocks of one launch run at
+    different times: the stage kernel that computes each zone's right-hand
+    side itself (the plain path) and the Newton kernel that reads it from the
+    rhs kernel
     (taken here with a network guess that is rejected in every zone) both
     match the oracle's third step.  The two evaluate the same formulas in
     different kernels, where the compiler may fuse different multiply-adds,
