@@ -555,17 +555,6 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     if (a.stats) flush_stats(a, ls);
 }
 
-// ------------------------------------------------------------------ tiled stage
-//
-// One kernel per stage for 1- and 2-D Minkowski grids: a block of 256 threads
-// owns a tile of TX x TY zones (16 x 16 in 2-D, 256 in 1-D).  It stages the
-// tile's P^E with a two-cell halo in LDS, computes into LDS every face flux
-// its zones need (the x-faces of rows -1..TY, for the corner EMFs of
-// flux-CT, and the y-faces of columns -1..TX), then solves one zone per
-// thread, reading fluxes and P^E from LDS.
-// Fluxes never go to global memory and the stage is one launch; the price is
-// recomputing the faces shared with neighbouring tiles (2.4 faces per zone in
-// 2-D against 2.0).
 // Exchange a double with the other lane of its pair (lanes 2m and 2m + 1):
 // DPP quad permutation [1, 0, 3, 2].  Every lane of the wave must be active.
 __device__ __forceinline__ double pair_swap(double x)
@@ -611,6 +600,17 @@ __device__ __forceinline__ void llf_pair(const Phys& ph, const GeoMink& g, const
     }
 }
 
+// ------------------------------------------------------------------ tiled stage
+//
+// One kernel per stage for 1- and 2-D Minkowski grids: a block of 256 threads
+// owns a tile of TX x TY zones (16 x 16 in 2-D, 256 in 1-D).  It stages the
+// tile's P^E with a two-cell halo in LDS, computes into LDS every face flux
+// its zones need (the x-faces of rows -1..TY, for the corner EMFs of
+// flux-CT, and the y-faces of columns -1..TX), then solves one zone per
+// thread, reading fluxes and P^E from LDS.
+// Fluxes never go to global memory and the stage is one launch; the price is
+// recomputing the faces shared with neighbouring tiles (2.4 faces per zone in
+// 2-D against 2.0).
 template <int ND>
 struct Tile {
     static constexpr int TX = ND == 1 ? 256 : 16, TY = ND == 1 ? 1 : 16;
