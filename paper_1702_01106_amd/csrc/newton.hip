@@ -644,6 +644,8 @@ struct SrcTile {
     __device__ __forceinline__ double Pn(int v, long) const { return pn[v]; }
 };
 
+// Held to 256 registers (two waves per SIMD): with 79 KiB of LDS a block,
+// two tiles then share a CU whenever the grid has more tiles than CUs.
 template <int NV, int ND, typename JT>
 __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(NewtonArgs a)
 {
