@@ -281,8 +281,8 @@ def main() -> int:
     flops = newton_flops(nvar, st_p["zone_stages"], (st_p["mean_iters"][0] + st_p["mean_iters"][1]) * zones
                          * args.steps, st_p["n_resid_calls"])
     per_launch_flops = flops / max(n_newton, 1)
-    # on a 1- or 2-D Minkowski grid whose tiles fit the device the stage is
-    # one kernel (faces, right-hand side and Newton); its algorithmic flops
+    # on a 1- or 2-D Minkowski grid without the network the stage is one
+    # kernel (faces, right-hand side and Newton); its algorithmic flops
     # count every face once and every zone's right-hand side once
     tiled = times.get("face_flux", (0.0, 0))[1] == 0 and wl["ndim"] == 2 and wl["metric"] == "minkowski"
     if tiled:

@@ -189,8 +189,6 @@ hipError_t launch_explicit_stage(const StageArgs& a, int nvar, int metric, hipSt
 hipError_t launch_fluxes(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_rhs(const StageArgs& a, int nvar, int metric, hipStream_t st);
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st);
-// blocks (tiles) of the tiled stage kernel for a 1- or 2-D layout
-long stage_tiles(const Layout& L);
 hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const double* P, double* R, double* rnorm,
                            hipStream_t st);
 hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int nvar, int metric, const double* P,

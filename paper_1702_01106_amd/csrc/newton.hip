@@ -866,12 +866,6 @@ hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 
 }  // namespace
 
-long stage_tiles(const Layout& L)
-{
-    if (L.ndim == 1) return (L.n[0] + Tile<1>::TX - 1) / Tile<1>::TX;
-    return (long)((L.n[0] + Tile<2>::TX - 1) / Tile<2>::TX) * ((L.n[1] + Tile<2>::TY - 1) / Tile<2>::TY);
-}
-
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st)
 {
     if (nvar == 8) return metric == 0 ? newton_t<8, GeoMink>(a, jac_f32, st) : newton_t<8, GeoKS>(a, jac_f32, st);
