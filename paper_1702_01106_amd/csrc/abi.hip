@@ -62,6 +62,7 @@ struct grim_ctx {
     // from buffer p (an even count, so the step after it starts from p again)
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     double graph_dt = 0.0;
+    int cus = 0;  // compute units of the device (0 if the query failed)
     bool timing = false;
     struct Mark {
         int group;
@@ -196,6 +197,7 @@ StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp
 NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
 {
     NewtonArgs a{};
+    a.cus = c->cus;
     a.s = s;
     a.tol = c->cfg.tol;
     a.eps = c->cfg.eps_fd;
@@ -404,6 +406,12 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
             delete c;
             return GRIM_E_HIP;
         }
+    }
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            c->cus = 0;
     }
     c->nvar = cfg->model;
     Layout& L = c->L;

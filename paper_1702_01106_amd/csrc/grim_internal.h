@@ -180,6 +180,9 @@ struct NewtonArgs {
     // kernel is not launched; FP32-Jacobian failures are retried in FP64 in
     // the same lane)
     int tiled;
+    // compute units of the device (0 if unknown): a 2-D tiled stage whose
+    // tiles all fit at once runs 512-thread blocks (see k_stage)
+    int cus;
 };
 constexpr uint8_t kFlagRetry = 32;
 

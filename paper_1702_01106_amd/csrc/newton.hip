@@ -645,10 +645,15 @@ struct SrcTile {
 };
 
 // Held to 256 registers (two waves per SIMD): with 79 KiB of LDS a block,
-// two tiles then share a CU whenever the grid has more tiles than CUs.
-template <int NV, int ND, typename JT>
-__global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(NewtonArgs a)
+// two tiles then share a CU whenever the grid has more tiles than CUs.  When
+// every tile fits at once (one per CU), 2-D blocks have kBlock = 512 threads
+// instead: waves 4-7 stage P^E and compute the y-faces beside waves 0-3 (the
+// x-faces), so the face phase runs two waves per SIMD, and then leave the
+// zones to waves 0-3.
+template <int NV, int ND, typename JT, int kBlock>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(NewtonArgs a)
 {
+    static_assert(kBlock == Tile<ND>::kThreads || (ND == 2 && kBlock == 2 * Tile<ND>::kThreads), "block size");
     using T = Tile<ND>;
     __shared__ double lds[T::template words<NV>()];
     double* pe = lds;
@@ -673,14 +678,14 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per
     double pn[NV];
     {
         const int gi0 = x0 + L.g[0] - 2, gj0 = y0 + L.g[1] - T::HY;
-        constexpr int cells = T::PY * T::PX, rounds = (cells + T::kThreads - 1) / T::kThreads;
+        constexpr int cells = T::PY * T::PX, rounds = (cells + kBlock - 1) / kBlock;
         double b[rounds][NV];
 #pragma unroll
         for (int r = 0; r < rounds; ++r) {
             // a cell outside the tile or the grid reads cell 0 instead and is
             // multiplied by zero: no load sits in a branch, whose end would
             // have to wait for it
-            const int cq = tid + r * T::kThreads;
+            const int cq = tid + r * kBlock;
             const int gi = gi0 + cq % T::PX, gj = gj0 + cq / T::PX;
             const bool in = cq < cells && gi < L.N[0] && gj < L.N[1];
             const double keep = in ? 1.0 : 0.0;
@@ -696,7 +701,7 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per
         }
 #pragma unroll
         for (int r = 0; r < rounds; ++r) {
-            const int cq = tid + r * T::kThreads;
+            const int cq = tid + r * kBlock;
             if (r < rounds - 1 || cq < cells) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) pe[v * cells + cq] = b[r][v];
@@ -739,12 +744,22 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per
         for (int v = 0; v < NV; ++v) fy[(v * T::YY + ey) * T::YX + ex + 1] = f[v];
     };
     if constexpr (ND >= 2) {
-        {
+        if constexpr (kBlock == T::kThreads) {
             double f0[NV], f1[NV];
             xface(tid, f0);
             yface(tid, f1);
             xstore(tid, f0);
             ystore(tid, f1);
+        } else {
+            // waves 0-3 the x-faces, waves 4-7 the y-faces (wave-uniform)
+            double f0[NV];
+            if (tid < T::kThreads) {
+                xface(tid, f0);
+                xstore(tid, f0);
+            } else {
+                yface(tid - T::kThreads, f0);
+                ystore(tid - T::kThreads, f0);
+            }
         }
         // the remaining faces, each by a pair of lanes (half a face's chain
         // per lane): waves 0-1 take the x-faces and waves 2-3 the y-faces, a
@@ -761,7 +776,7 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per
             const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
             llf_pair<NV, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, right, f2);
             if (!right && (e >> 1) < nxf - T::kThreads) xstore(q, f2);
-        } else {
+        } else if (tid < T::kThreads) {
             const int q = T::kThreads + min(e >> 1, nyf - T::kThreads - 1);
             const int ex = q % T::YX - 1, ey = q / T::YX;
             const double* p = pe + (ey + T::HY) * T::PX + ex + 2;
@@ -806,7 +821,7 @@ __global__ __launch_bounds__(Tile<ND>::kThreads) __attribute__((amdgpu_waves_per
         zs_finish<NV, GeoMink>(a, s, false, ls);
         ls.nrt = retried;
     }
-    if (a.stats) flush_stats(a, ls);
+    if (a.stats && tid < T::kThreads) flush_stats(a, ls);  // waves 4-7 solve no zone
 }
 
 template <int NV, int ND>
@@ -816,10 +831,18 @@ hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
     const long tiles = (long)((a.s.L.n[0] + T::TX - 1) / T::TX) * ((a.s.L.n[1] + T::TY - 1) / T::TY);
     NewtonArgs b = a;
     b.pass = 0;
-    if (jac_f32)
-        hipLaunchKernelGGL((k_stage<NV, ND, float>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
-    else
-        hipLaunchKernelGGL((k_stage<NV, ND, double>), dim3((unsigned)tiles), dim3(T::kThreads), 0, st, b);
+    // 512-thread blocks (face phase at two waves per SIMD) while every tile
+    // fits the device at once; past that, 256-thread blocks two to a CU
+    constexpr int kWide = ND == 2 ? 2 * T::kThreads : T::kThreads;
+    const bool wide = ND == 2 && a.cus > 0 && tiles <= a.cus;
+    const dim3 grid((unsigned)tiles);
+    if (jac_f32) {
+        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, float, kWide>), grid, dim3(kWide), 0, st, b);
+        else hipLaunchKernelGGL((k_stage<NV, ND, float, T::kThreads>), grid, dim3(T::kThreads), 0, st, b);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, double, kWide>), grid, dim3(kWide), 0, st, b);
+        else hipLaunchKernelGGL((k_stage<NV, ND, double, T::kThreads>), grid, dim3(T::kThreads), 0, st, b);
+    }
     return hipGetLastError();
 }
 
