@@ -738,16 +738,22 @@ void oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x, const d
  *  - norm: ||R|| = nscale * sqrt(sum R_v^2)
  *  - stop when ||R|| < tol (iters = number of linear solves), or at k_max
  *  - Jacobian by oracle_fd_jacobian
- *  - line search: accept if ||R(P + lam dP)|| < ||R(P)|| (1 - eps_bt lam);
- *    otherwise lam <- quadratic backtrack clamped to [0.1 lam, 0.5 lam];
- *    a non-finite trial halves lam;
- *    after ls_max trials the last finite trial is taken (flag LS_EXHAUSTED). */
+ *  - line search (Sec. 3.2): lambda = 1; accept if
+ *    ||R(P + lam dP)|| < ||R(P)|| (1 - eps_bt lam); otherwise lambda becomes
+ *    the minimiser of the quadratic model (oracle_ls_lambda) and the trial is
+ *    repeated.  Readings where the paper is silent: a non-finite trial halves
+ *    lambda; after ls_max trials the last finite trial is taken (flag
+ *    LS_EXHAUSTED).  ls_safeguard = 1 keeps each new lambda in [0.1, 0.5] of
+ *    the previous one (the usual safeguard of quadratic backtracking); 0
+ *    applies the printed update unchanged.
+ *  - backtracks: the rejected trials, summed over the iterations. */
 int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nscale, double tol, double eps,
-                          double eps_bt, int k_max, int ls_max, int32_t* iters, double* resid, uint8_t* flags)
+                          double eps_bt, int k_max, int ls_max, int ls_safeguard, int32_t* iters, double* resid,
+                          uint8_t* flags, int32_t* backtracks)
 {
     double R[16], J[256], dx[16], xt[16], Rt[16], negR[16];
     uint8_t fl = 0;
-    int k = 0;
+    int k = 0, nbt = 0;
     if (n > 16) return 2;
     fn(ctx, x, R);
     double r = o_norm(n, R, nscale);
@@ -770,17 +776,16 @@ int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nsca
                 for (int q = 0; q < n; ++q) { xf[q] = xt[q]; Rf[q] = Rt[q]; }
                 rf = rt;
                 if (rt < r * (1.0 - eps_bt * lam)) { accepted = 1; break; }
-                /* minimiser of the quadratic model, safeguarded to
-                 * [0.1, 0.5] of the previous lambda (reading: the paper's
-                 * update has no lower bound; without one, a full step far
-                 * worse than f(0) yields lambda ~ 1e-4 and Newton stalls) */
                 double ln = oracle_ls_lambda(f0, rt * rt, lam);
-                if (!(ln >= 0.1 * lam)) ln = 0.1 * lam;
-                if (ln > 0.5 * lam) ln = 0.5 * lam;
+                if (ls_safeguard) {
+                    if (!(ln >= 0.1 * lam)) ln = 0.1 * lam;
+                    if (ln > 0.5 * lam) ln = 0.5 * lam;
+                }
                 lam = ln;
             } else {
                 lam *= 0.5;
             }
+            ++nbt;
         }
         if (!accepted) {
             fl |= OFLAG_LS_EXHAUSTED;
@@ -793,6 +798,7 @@ int oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x, double nsca
     if (iters) *iters = k;
     if (resid) *resid = r;
     if (flags) *flags = fl;
+    if (backtracks) *backtracks = nbt;
     return 0;
 }
 
@@ -910,21 +916,19 @@ static void o_zone_setup(const ocfg_t* c, const double X[4], const double* Pn, c
 /* one stage of the two-stage scheme                                         */
 /* ------------------------------------------------------------------------ */
 
-int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* guess,
-                 double* Pout, int32_t* iters, double* resid, uint8_t* flags)
+/* One stage (Sec. 2.3) on a ghost-filled P^E: the explicit stage, then the
+ * Newton solve of every interior zone from P_n (or the supplied guess). */
+static int o_stage_core(const ocfg_t* c, const olay_t* Lp, const double* Pn, const double* PEg, double dtp,
+                        const double* guess, double* Pout, int32_t* iters, double* resid, uint8_t* flags,
+                        int32_t* backtracks)
 {
-#ifdef _OPENMP
-    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
-#endif
-    olay_t L = o_layout(c);
+    olay_t L = *Lp;
     const int nv = c->nvar;
     const size_t nz = o_zones(&L);
-    double* PEg = (double*)calloc((size_t)nv * L.cells, sizeof(double));
     double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
     double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
     oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
-    if (!PEg || !divF || !srcE || !sp) { free(PEg); free(divF); free(srcE); free(sp); return -1; }
-    o_to_ghosted(c, &L, PE, PEg);
+    if (!divF || !srcE || !sp) { free(divF); free(srcE); free(sp); return -1; }
     o_explicit_stage(c, &L, PEg, divF, srcE, sp);
 
 #pragma omp parallel for collapse(2) schedule(static)
@@ -932,11 +936,12 @@ int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp
         for (int jj = 0; jj < L.n[1]; ++jj)
             for (int ii = 0; ii < L.n[0]; ++ii) {
                 size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                size_t m = o_cell(&L, ii + L.g[0], jj + L.g[1], kk + L.g[2]);
                 double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX], P[NVMAX];
                 o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
                 for (int v = 0; v < nv; ++v) {
                     pn[v] = Pn[(size_t)v * nz + z];
-                    pe[v] = PE[(size_t)v * nz + z];
+                    pe[v] = PEg[(size_t)v * L.cells + m];
                     dz[v] = divF[(size_t)v * nz + z];
                     sz[v] = srcE[(size_t)v * nz + z];
                 }
@@ -948,7 +953,7 @@ int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp
                 for (int i = 0; i < 3; ++i)
                     P[B1 + i] = (Z.Un[B1 + i] + dtp * Z.expl[B1 + i]) / Z.G.gdet;
                 double urho_n = Z.Un[RHO];
-                int32_t it = 0;
+                int32_t it = 0, bt = 0;
                 double rr = 0.0;
                 uint8_t fl = 0;
                 oreduced_t Q;
@@ -958,7 +963,7 @@ int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp
                 double x[7];
                 for (int i = 0; i < Q.m; ++i) x[i] = P[o_unknown[i]];
                 oracle_newton_generic(Q.m, o_reduced_residual, &Q, x, dtp / urho_n, c->tol, c->eps, c->eps_bt,
-                                      c->k_max, c->ls_max, &it, &rr, &fl);
+                                      c->k_max, c->ls_max, c->ls_safeguard, &it, &rr, &fl, &bt);
                 for (int i = 0; i < Q.m; ++i) P[o_unknown[i]] = x[i];
                 if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= OFLAG_UNPHYSICAL;
                 if (c->floors) {
@@ -971,16 +976,41 @@ int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp
                 if (iters) iters[z] = it;
                 if (resid) resid[z] = rr;
                 if (flags) flags[z] = fl;
+                if (backtracks) backtracks[z] = bt;
             }
-    free(PEg);
     free(divF);
     free(srcE);
     free(sp);
     return 0;
 }
 
+int oracle_stage(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* guess,
+                 double* Pout, int32_t* iters, double* resid, uint8_t* flags)
+{
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    olay_t L = o_layout(c);
+    double* PEg = (double*)calloc((size_t)c->nvar * L.cells, sizeof(double));
+    if (!PEg) return -1;
+    o_to_ghosted(c, &L, PE, PEg);
+    int rc = o_stage_core(c, &L, Pn, PEg, dtp, guess, Pout, iters, resid, flags, NULL);
+    free(PEg);
+    return rc;
+}
+
+int oracle_stage_ghosted(const ocfg_t* c, const double* Pn, const double* PEg, double dtp, const double* guess,
+                         double* Pout, int32_t* iters, double* resid, uint8_t* flags, int32_t* backtracks)
+{
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    olay_t L = o_layout(c);
+    return o_stage_core(c, &L, Pn, PEg, dtp, guess, Pout, iters, resid, flags, backtracks);
+}
+
 static void o_accumulate(ostats_t* st, int stage, size_t nz, const int32_t* it, const double* rr,
-                         const uint8_t* fl)
+                         const uint8_t* fl, const int32_t* bt)
 {
     if (!st) return;
     st->zones = (int64_t)nz;
@@ -991,6 +1021,7 @@ static void o_accumulate(ostats_t* st, int stage, size_t nz, const int32_t* it, 
         if (fl[z] & OFLAG_LS_EXHAUSTED) st->n_ls_exhausted++;
         if (fl[z] & OFLAG_UNPHYSICAL) st->n_unphysical++;
         if (rr[z] > st->max_resid || !isfinite(rr[z])) st->max_resid = rr[z];
+        st->n_backtracks += bt[z];
     }
 }
 
@@ -999,25 +1030,36 @@ static void o_accumulate(ostats_t* st, int stage, size_t nz, const int32_t* it, 
  * Both solves start from P_n. */
 int oracle_step(const ocfg_t* c, double* P, double dt, ostats_t* st)
 {
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
     olay_t L = o_layout(c);
     const size_t nz = o_zones(&L);
     const size_t nvz = (size_t)c->nvar * nz;
     double* Ph = (double*)malloc(nvz * sizeof(double));
     double* P1 = (double*)malloc(nvz * sizeof(double));
+    double* Pg = (double*)calloc((size_t)c->nvar * L.cells, sizeof(double));
     int32_t* it = (int32_t*)malloc(nz * sizeof(int32_t));
+    int32_t* bt = (int32_t*)malloc(nz * sizeof(int32_t));
     double* rr = (double*)malloc(nz * sizeof(double));
     uint8_t* fl = (uint8_t*)malloc(nz);
     int rc = -1;
-    if (Ph && P1 && it && rr && fl) {
-        rc = oracle_stage(c, P, P, 0.5 * dt, NULL, Ph, it, rr, fl);
-        o_accumulate(st, 0, nz, it, rr, fl);
-        if (rc == 0) rc = oracle_stage(c, P, Ph, dt, NULL, P1, it, rr, fl);
-        o_accumulate(st, 1, nz, it, rr, fl);
+    if (Ph && P1 && Pg && it && bt && rr && fl) {
+        o_to_ghosted(c, &L, P, Pg);
+        rc = o_stage_core(c, &L, P, Pg, 0.5 * dt, NULL, Ph, it, rr, fl, bt);
+        o_accumulate(st, 0, nz, it, rr, fl, bt);
+        if (rc == 0) {
+            o_to_ghosted(c, &L, Ph, Pg);
+            rc = o_stage_core(c, &L, P, Pg, dt, NULL, P1, it, rr, fl, bt);
+        }
+        o_accumulate(st, 1, nz, it, rr, fl, bt);
         if (rc == 0) memcpy(P, P1, nvz * sizeof(double));
     }
     free(Ph);
     free(P1);
+    free(Pg);
     free(it);
+    free(bt);
     free(rr);
     free(fl);
     return rc;
@@ -1196,6 +1238,15 @@ int oracle_sum_U(const ocfg_t* c, const double* P, double* sums)
 /* ------------------------------------------------------------------------ */
 /* point functions exported for the pins                                     */
 /* ------------------------------------------------------------------------ */
+
+/* Interior primitives -> ghosted grid with every ghost cell filled by the
+ * boundary conditions (o_fill_ghosts). */
+int oracle_fill_ghosts(const ocfg_t* c, const double* Pint, double* Pg)
+{
+    olay_t L = o_layout(c);
+    o_to_ghosted(c, &L, Pint, Pg);
+    return 0;
+}
 
 void oracle_geometry(const ocfg_t* c, const double* X, double* gcov, double* gcon, double* gdet, double* alpha)
 {

@@ -36,6 +36,8 @@ typedef struct {
     double theta_plm;      /* generalized-minmod parameter                    */
     double tol, eps, eps_bt;
     int k_max, ls_max;
+    int ls_safeguard;      /* 0: the update of Sec. 3.2 as printed; 1: each new
+                              lambda kept in [0.1, 0.5] of the previous one  */
     int floors;            /* 1: rho >= rho_fl r^-3/2, u >= u_fl r^-5/2        */
     double rho_fl, u_fl;
     int nthreads;          /* OpenMP threads, 0 = runtime default             */
@@ -49,6 +51,7 @@ typedef struct {
     int64_t n_ls_exhausted;
     int64_t n_unphysical;
     double max_resid;
+    int64_t n_backtracks;  /* rejected line-search trials, summed over zones */
 } ostats_t;
 
 /* per-zone flags */
@@ -61,6 +64,15 @@ typedef struct {
 int    oracle_stage(const ocfg_t* c, const double* Pn, const double* PE,
                     double dtp, const double* guess, double* Pout,
                     int32_t* iters, double* resid, uint8_t* flags);
+/* As oracle_stage, with P^E given on the ghosted grid ([nvar][N3][N2][N1],
+ * N = n + 2 ng on active directions): its ghosts are used as they are, not
+ * refilled from the boundary conditions, so a subdomain of a larger grid can
+ * be advanced with the halo taken from that grid.  backtracks (may be NULL)
+ * receives the rejected line-search trials of every zone. */
+int    oracle_stage_ghosted(const ocfg_t* c, const double* Pn, const double* PEg,
+                            double dtp, const double* guess, double* Pout,
+                            int32_t* iters, double* resid, uint8_t* flags,
+                            int32_t* backtracks);
 int    oracle_step(const ocfg_t* c, double* P, double dt, ostats_t* st);
 int    oracle_run(const ocfg_t* c, double* P, double dt, int nsteps, ostats_t* st);
 int    oracle_residual(const ocfg_t* c, const double* Pn, const double* PE,
@@ -82,12 +94,16 @@ typedef void (*oresid_fn)(void* ctx, const double* x, double* r);
 int    oracle_newton_generic(int n, oresid_fn fn, void* ctx, double* x,
                              double nscale, double tol, double eps,
                              double eps_bt, int k_max, int ls_max,
-                             int32_t* iters, double* resid, uint8_t* flags);
+                             int ls_safeguard, int32_t* iters, double* resid,
+                             uint8_t* flags, int32_t* backtracks);
 void   oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x,
                           const double* R, double eps, double* J);
 int    oracle_zone_jacobian(const ocfg_t* c, const double* Pn, const double* PE,
                             double dtp, const double* P, long z, double* J,
                             double* Rz);
+/* Interior P [nvar][n3][n2][n1] -> ghosted Pg [nvar][N3][N2][N1] with the
+ * ghosts filled by the boundary conditions of c. */
+int    oracle_fill_ghosts(const ocfg_t* c, const double* Pint, double* Pg);
 int    oracle_divb(const ocfg_t* c, const double* P, double* divb);
 int    oracle_sum_U(const ocfg_t* c, const double* P, double* sums);
 

@@ -38,7 +38,7 @@ class OCfg(C.Structure):
         ("gam", C.c_double), ("tau_R", C.c_double), ("chi", C.c_double), ("nu", C.c_double),
         ("theta_plm", C.c_double),
         ("tol", C.c_double), ("eps", C.c_double), ("eps_bt", C.c_double),
-        ("k_max", C.c_int), ("ls_max", C.c_int),
+        ("k_max", C.c_int), ("ls_max", C.c_int), ("ls_safeguard", C.c_int),
         ("floors", C.c_int), ("rho_fl", C.c_double), ("u_fl", C.c_double),
         ("nthreads", C.c_int),
     ]
@@ -48,7 +48,7 @@ class OStats(C.Structure):
     _fields_ = [
         ("iters_sum", C.c_double * 2), ("zones", C.c_int64), ("max_iters", C.c_int32),
         ("n_fail", C.c_int64), ("n_ls_exhausted", C.c_int64), ("n_unphysical", C.c_int64),
-        ("max_resid", C.c_double),
+        ("max_resid", C.c_double), ("n_backtracks", C.c_int64),
     ]
 
     def as_dict(self, nsteps: int) -> dict:
@@ -60,6 +60,7 @@ class OStats(C.Structure):
             "n_ls_exhausted": int(self.n_ls_exhausted),
             "n_unphysical": int(self.n_unphysical),
             "max_resid": float(self.max_resid),
+            "n_backtracks": int(self.n_backtracks),
         }
 
 
@@ -101,6 +102,7 @@ def cfg_from_dict(d: dict) -> OCfg:
     c.eps_bt = d.get("eps_bt", 1e-4)
     c.k_max = d.get("k_max", 20)
     c.ls_max = d.get("ls_max", 10)
+    c.ls_safeguard = int(d.get("ls_safeguard", 0))
     c.floors = 1 if d.get("floors", False) else 0
     c.rho_fl = d.get("rho_floor", 1e-5)
     c.u_fl = d.get("u_floor", 1e-7)
@@ -121,6 +123,7 @@ class Oracle:
             L = C.CDLL(_LIB)
             P = C.POINTER(OCfg)
             L.oracle_stage.argtypes = [P, _D, _D, C.c_double, _D, _D, _I32, _D, _U8]
+            L.oracle_stage_ghosted.argtypes = [P, _D, _D, C.c_double, _D, _D, _I32, _D, _U8, _I32]
             L.oracle_step.argtypes = [P, _D, C.c_double, C.POINTER(OStats)]
             L.oracle_run.argtypes = [P, _D, C.c_double, C.c_int, C.POINTER(OStats)]
             L.oracle_residual.argtypes = [P, _D, _D, C.c_double, _D, _D, _D]
@@ -137,8 +140,10 @@ class Oracle:
             L.oracle_ls_lambda.argtypes = [C.c_double, C.c_double, C.c_double]
             L.oracle_ls_lambda.restype = C.c_double
             L.oracle_newton_generic.argtypes = [C.c_int, RESID_FN, C.c_void_p, _D, C.c_double, C.c_double,
-                                                C.c_double, C.c_double, C.c_int, C.c_int, _I32, _D, _U8]
+                                                C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _I32, _D, _U8,
+                                                _I32]
             L.oracle_divb.argtypes = [P, _D, _D]
+            L.oracle_fill_ghosts.argtypes = [P, _D, _D]
             L.oracle_fd_jacobian.argtypes = [C.c_int, RESID_FN, C.c_void_p, _D, _D, C.c_double, _D]
             L.oracle_zone_jacobian.argtypes = [P, _D, _D, C.c_double, _D, C.c_long, _D, _D]
             L.oracle_sum_U.argtypes = [P, _D, _D]
@@ -170,6 +175,28 @@ class Oracle:
                                  it.ctypes.data_as(_I32), _dp(rr), fl.ctypes.data_as(_U8))
         assert rc == 0
         return out, it, rr, fl
+
+    def stage_ghosted(self, Pn, PEg, dtp, guess=None):
+        """One stage with P^E given on the ghosted grid [nvar][N3][N2][N1]
+        (ghosts used as given).  Returns (P, iters, resid, flags, backtracks)."""
+        Pn = self._arr(Pn)
+        PEg = np.ascontiguousarray(PEg, dtype=np.float64)
+        g = self.cfg.ng
+        nd = self.cfg.ndim
+        N = [self.shape[3] + 2 * g, self.shape[2] + (2 * g if nd >= 2 else 0),
+             self.shape[1] + (2 * g if nd >= 3 else 0)]
+        assert PEg.size == self.nvar * N[0] * N[1] * N[2], (PEg.shape, N)
+        gu = None if guess is None else self._arr(guess)
+        out = np.empty(self.shape)
+        it = np.empty(self.nz, dtype=np.int32)
+        rr = np.empty(self.nz)
+        fl = np.empty(self.nz, dtype=np.uint8)
+        bt = np.empty(self.nz, dtype=np.int32)
+        rc = self.L.oracle_stage_ghosted(C.byref(self.cfg), _dp(Pn), _dp(PEg), dtp, _dp(gu), _dp(out),
+                                         it.ctypes.data_as(_I32), _dp(rr), fl.ctypes.data_as(_U8),
+                                         bt.ctypes.data_as(_I32))
+        assert rc == 0
+        return out, it, rr, fl, bt
 
     def step(self, P, dt, nsteps=1):
         P = self._arr(P).copy()
@@ -203,6 +230,17 @@ class Oracle:
 
     def cfl_dt(self, P, cfl):
         return float(self.L.oracle_cfl_dt(C.byref(self.cfg), _dp(self._arr(P)), cfl))
+
+    def ghosted_shape(self):
+        g, nd = self.cfg.ng, self.cfg.ndim
+        return (self.nvar, self.shape[1] + (2 * g if nd >= 3 else 0), self.shape[2] + (2 * g if nd >= 2 else 0),
+                self.shape[3] + 2 * g)
+
+    def fill_ghosts(self, P):
+        """Interior P -> ghosted array with the boundary conditions applied."""
+        out = np.empty(self.ghosted_shape())
+        self.L.oracle_fill_ghosts(C.byref(self.cfg), _dp(self._arr(P)), _dp(out))
+        return out
 
     def divb(self, P):
         out = np.empty(self.nz)
@@ -280,8 +318,9 @@ class Oracle:
 
     @classmethod
     def newton(cls, fn, x0, tol=1e-10, eps=1.4901161193847656e-08, eps_bt=1e-4, k_max=20, ls_max=10,
-               nscale=1.0):
-        """Newton driver on a Python residual fn(x: ndarray) -> ndarray."""
+               nscale=1.0, ls_safeguard=0, with_backtracks=False):
+        """Newton driver on a Python residual fn(x: ndarray) -> ndarray.
+        Returns (x, iters, resid, flags[, backtracks])."""
         n = len(x0)
         x = np.ascontiguousarray(x0, dtype=np.float64).copy()
 
@@ -295,6 +334,9 @@ class Oracle:
         it = C.c_int32()
         rr = C.c_double()
         fl = C.c_uint8()
+        bt = C.c_int32()
         cls.lib().oracle_newton_generic(n, cfn, None, _dp(x), nscale, tol, eps, eps_bt, k_max, ls_max,
-                                        C.byref(it), C.byref(rr), C.byref(fl))
+                                        int(ls_safeguard), C.byref(it), C.byref(rr), C.byref(fl), C.byref(bt))
+        if with_backtracks:
+            return x, it.value, rr.value, fl.value, bt.value
         return x, it.value, rr.value, fl.value

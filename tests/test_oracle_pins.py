@@ -244,6 +244,54 @@ def test_ls_update_is_quadratic_minimiser(oracle_mod):
                 assert abs(O.ls_lambda(f0, f1, lam) - f0 / c) <= 1e-13 * f0 / c
 
 
+def test_line_search_backtracks_by_hand(oracle_mod):
+    """Sec. 3.2 on R = arctan(x) from x0 = 3, worked by hand:
+    k = 0: dx = -atan(3)(1 + 9) = -12.49; the full step gives
+    |atan(-9.49)| = 1.466 > 1.249, rejected; lambda = f0/(f1 + f0) = 0.421
+    (f = R^2), x = -2.255, |R| = 1.153 accepted.  k = 1: dx = 7.01; the full
+    step gives atan(4.76) = 1.364 > 1.153, rejected; lambda = 0.417,
+    x = 0.666 accepted.  From there |x| < 1.39 and plain Newton converges.
+    So exactly two rejected trials, and the same with the safeguard (both
+    lambdas lie in [0.1, 0.5])."""
+    O = oracle_mod.Oracle
+    for sg in (0, 1):
+        x, it, rr, fl, bt = O.newton(lambda x: np.arctan(x), np.array([3.0]), ls_safeguard=sg, with_backtracks=True)
+        assert fl == 0 and bt == 2 and abs(x[0]) < 1e-10, (sg, x, it, bt)
+
+
+def test_paper_update_stalls_in_kerr_atmosphere(oracle_mod):
+    """Why the Kerr workloads use the safeguarded update.  With the update of
+    Sec. 3.2 as printed, a full Newton step far worse than f(0) gives
+    lambda ~ f(0)/f(1), and in floor-level atmosphere next to the torus
+    (r ~ 11, high latitude) Newton then crawls: on the 28 x 24 x 6 EMHD torus
+    the first full step leaves zones at k_max.  Keeping each new lambda in
+    [0.1, 0.5] of the previous one (the usual safeguard of quadratic
+    backtracking) converges every zone, to the same root elsewhere."""
+    from paper_1702_01106_amd import workloads as W
+
+    res = {}
+    for sg in (0, 1):
+        wl = W.small("emhd3d_kerr_192", [28, 24, 6], ls_safeguard=sg)
+        P = W.kerr_torus(wl, seed=0)
+        o = oracle_mod.Oracle(wl)
+        dt = o.cfl_dt(P, 0.5)
+        Ph, it, rr, fl = o.stage(P, P, 0.5 * dt)
+        P1, it2, rr2, fl2 = o.stage(P, Ph, dt)
+        res[sg] = (P1, fl2, it2)
+    P0, fl0, it0 = res[0]
+    P1, fl1, it1 = res[1]
+    bad = fl0 != 0
+    assert bad.sum() >= 10 and np.all(fl0[bad] == oracle_mod.FLAGS["NOT_CONVERGED"]) and np.all(it0[bad] == 20)
+    assert np.all(fl1 == 0)
+    X1, _, _ = W.zone_centres(W.small("emhd3d_kerr_192", [28, 24, 6]))
+    r = np.exp(X1).ravel()[bad]
+    assert r.min() > 5.0 and r.max() < 20.0, r
+    good = ~bad
+    from tests.helpers import prim_rel_err
+
+    assert prim_rel_err(P0, P1).reshape(10, -1)[:, good].max() < 1e-6
+
+
 def test_newton_generic_behaviour(oracle_mod):
     O = oracle_mod.Oracle
     rng = np.random.default_rng(1)
@@ -259,9 +307,14 @@ def test_newton_generic_behaviour(oracle_mod):
     # far start on a saturating residual: several rejected trials per step
     x, it, rr, fl = O.newton(lambda x: np.arctan(x), np.array([20.0]))
     assert fl == 0 and abs(x[0]) < 1e-10 and it <= 20
-    # no real root: never reports convergence
+    # no real root: never reports convergence, stops at k_max
     x, it, rr, fl = O.newton(lambda x: x * x + 1.0, np.array([0.5]), k_max=6)
-    assert fl & (oracle_mod.FLAGS["NOT_CONVERGED"] | oracle_mod.FLAGS["SINGULAR"]) and rr > 1e-10
+    assert fl == oracle_mod.FLAGS["NOT_CONVERGED"] and it == 6 and rr > 1e-10
+    # with the safeguarded update the steps reach the minimiser of |R| at
+    # x = 0, where R' = 2x is below what a forward difference of R ~ 1 can
+    # resolve: the Jacobian is an exact zero and the solve reports SINGULAR
+    x, it, rr, fl = O.newton(lambda x: x * x + 1.0, np.array([0.5]), k_max=6, ls_safeguard=1)
+    assert fl == oracle_mod.FLAGS["SINGULAR"] and rr > 1e-10
     # singular Jacobian (second residual independent of x)
     x, it, rr, fl = O.newton(lambda x: np.array([x[0] - 1.0, 1.0 + 0 * x[1]]), np.array([0.0, 0.0]))
     assert fl & oracle_mod.FLAGS["SINGULAR"] and it == 0
