@@ -109,6 +109,15 @@ typedef struct {
     int guess;           /* GRIM_GUESS_PN or GRIM_GUESS_MLP                  */
     int floors;          /* 1: rho >= rho_floor r^-3/2, u >= u_floor r^-5/2   */
     double rho_floor, u_floor;
+    int ls_safeguard;    /* line search (Sec. 3.2): 0 takes each new lambda as
+                            the minimiser of the quadratic model, as the paper
+                            states it; 1 keeps it within [0.1, 0.5] of the
+                            previous lambda (the usual safeguard of quadratic
+                            backtracking)                                    */
+    int external_workspace; /* 0: grim_create allocates the device memory;
+                            1: it allocates none, and the caller hands over
+                            grim_workspace_bytes(cfg) bytes of device memory
+                            with grim_bind_workspace before any other call  */
 } grim_config_t;
 
 /* Per-call solver statistics (a13).  mean_iters is per zone per stage. */
@@ -124,6 +133,7 @@ typedef struct {
     int64_t n_resid_calls;  /* residual evaluations R(P), summed over zones  */
     int64_t n_fallback;     /* zones whose learned guess was rejected        */
     int64_t n_f64_retry;    /* zones solved again with the FP64 Jacobian     */
+    int64_t n_backtracks;   /* rejected line-search trials, summed over zones */
 } grim_stats_t;
 
 /* Adam training of the learned-guess network. */
@@ -136,9 +146,13 @@ typedef struct {
     uint64_t seed;       /* shuffling                                         */
 } grim_train_cfg_t;
 
-/* Create a context: validates cfg, allocates device buffers (ghosted
- * primitive arrays, face fluxes, edge EMFs, stage right-hand sides, per-zone
- * results, metric tables) and builds the metric tables (a1, Sec. 2.1).
+/* Create a context: validates cfg, takes the device memory of the workspace
+ * (ghosted primitive arrays of the state, the half step and the test hooks,
+ * face fluxes, stage right-hand sides and EMHD coefficients, per-zone
+ * results, statistics, metric tables of the grid of Sec. 2.1, the network's
+ * parameters and per-zone features) in one allocation, and builds the metric
+ * tables (a1).  With cfg->external_workspace = 1 it allocates no device
+ * memory: the context is unusable (GRIM_E_STATE) until grim_bind_workspace.
  * hip_stream: a hipStream_t owned by the caller, or NULL.
  * Errors: GRIM_E_INVALID_ARG (bad sizes or parameters), GRIM_E_OOM, GRIM_E_HIP. */
 int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out);
@@ -146,7 +160,22 @@ int grim_destroy(grim_ctx_t* ctx);
 const char* grim_last_error(const grim_ctx_t* ctx);
 const char* grim_last_global_error(void);
 
-/* Device bytes the context holds (for capacity planning). */
+/* Bytes of device memory the workspace of a context for cfg needs (the grid
+ * of Sec. 2.1 with its ghost layers, Sec. 5.3), or 0 if cfg is invalid (the
+ * reason in grim_last_global_error).  Training the network (grim_mlp_train,
+ * grim_mlp_backward) allocates its batch buffers separately. */
+size_t grim_workspace_bytes(const grim_config_t* cfg);
+
+/* Hand a context created with cfg.external_workspace = 1 its workspace:
+ * dev_ptr is device memory of at least grim_workspace_bytes(cfg) bytes,
+ * aligned to 256 bytes, owned by the caller (e.g. a PyTorch tensor), which
+ * must keep it alive and untouched until grim_destroy.  Clears the state,
+ * builds the metric tables and synchronises.  Once per context.
+ * Errors: GRIM_E_INVALID_ARG (null, misaligned or too small), GRIM_E_STATE
+ * (the context allocates its own workspace, or one is already bound). */
+int grim_bind_workspace(grim_ctx_t* ctx, void* dev_ptr, size_t bytes);
+
+/* Device bytes the context holds or has been given (for capacity planning). */
 size_t grim_device_bytes(const grim_ctx_t* ctx);
 
 /* Copy the interior primitives in (set) or out (get).  on_device != 0 means P
@@ -177,11 +206,13 @@ int grim_residual(grim_ctx_t* ctx, const double* Pn, const double* PE, double dt
 
 /* Test hook for a2-a12: one stage.  Flux stage on P^E, then the Newton solve
  * from guess (NULL: P_n) with B at its explicit update.  Outputs per zone:
- * P_out (interior layout), iterations, final scaled norm and flags; any of
- * iters / resid / flags may be NULL.  All pointers device. */
+ * P_out (interior layout), iterations, final scaled norm, flags and the
+ * rejected line-search trials (Sec. 3.2); any of iters / resid / flags /
+ * backtracks may be NULL.  All those pointers device.  stats (host, may be
+ * NULL) receives the statistics of this stage (in mean_iters[0]). */
 int grim_stage_solve(grim_ctx_t* ctx, const double* Pn, const double* PE, double dtp,
                      const double* guess, double* P_out, int32_t* iters, double* resid,
-                     uint8_t* flags);
+                     uint8_t* flags, int32_t* backtracks, grim_stats_t* stats);
 
 /* Test hook for a2-a6: divF (eq. fvm_formulation, with flux-CT), the explicit
  * geometric source sqrt(-g) T^k_l Gamma^l_{nu k} at P^E (eq. divT_explicit)
@@ -241,6 +272,17 @@ int grim_mlp_backward(grim_ctx_t* ctx, const float* X, const float* dY, int64_t 
  * NULL) receives the mean training loss of every epoch.  Synchronises. */
 int grim_mlp_train(grim_ctx_t* ctx, const float* X, const float* T, int64_t n, const grim_train_cfg_t* cfg,
                    double* loss_hist);
+
+/* Normalisation of the network from n training pairs X [n][32], T [n][16]
+ * (device): x_mean[c] and the unbiased standard deviation s_c of every input
+ * column, x_istd[c] = 1/s_c (0 for a column that is constant over the pairs),
+ * and y_scale[c] = the unbiased standard deviation of target column c for
+ * c < n_used, 0 otherwise (an output constant over the pairs or unused is held
+ * at exactly zero).  Sums in FP64, in a fixed order (deterministic).  Output
+ * arrays are host memory of 32, 32 and 16 doubles.  Synchronises.
+ * Errors: GRIM_E_INVALID_ARG (n < 2, n_used outside [1, 16], null pointers). */
+int grim_mlp_normalisation(grim_ctx_t* ctx, const float* X, const float* T, int64_t n, int n_used,
+                           double* x_mean, double* x_istd, double* y_scale);
 
 /* Training pairs from the plain FP64 solver: run nsteps full steps of size dt
  * (eager, guess P_n) and after every stage store the network inputs and the

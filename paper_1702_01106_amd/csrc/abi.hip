@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <random>
 #include <string>
 #include <vector>
@@ -36,6 +37,7 @@ struct grim_ctx {
     double* coef = nullptr;
     double* interior = nullptr;          // staging buffer, interior layout
     double* hookP[2] = {nullptr, nullptr};
+    double* nrm = nullptr;               // partial sums of grim_mlp_normalisation
     int32_t* iters = nullptr;
     double* resid = nullptr;
     uint8_t* flags = nullptr;
@@ -57,7 +59,10 @@ struct grim_ctx {
     int* mlp_idx = nullptr;
     long mlp_idx_cap = 0;
     double* dloss = nullptr;
-    size_t bytes = 0;
+    char* ws = nullptr;                  // the workspace every buffer above is carved from
+    bool own_ws = false;                 // allocated by grim_create (else bound by the caller)
+    size_t ws_bytes = 0;
+    size_t bytes = 0;                    // device bytes held: workspace + training buffers
     // graph[p]: one step from state buffer p; graph[2 + p]: kGraphSteps steps
     // from buffer p (an even count, so the step after it starts from p again)
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -86,6 +91,15 @@ int fail(grim_ctx* c, int code, const std::string& msg)
 int hip_fail(grim_ctx* c, hipError_t e, const char* what)
 {
     return fail(c, GRIM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// A context whose device memory is in place (create allocated it, or a
+// workspace was bound).
+int usable(grim_ctx* c)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!c->ws) return fail(c, GRIM_E_STATE, "no workspace bound (grim_bind_workspace)");
+    return GRIM_OK;
 }
 
 #define HIP_TRY(c, expr)                                        \
@@ -119,14 +133,14 @@ void release(grim_ctx* c)
         if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->own_st && c->st) hipStreamDestroy(c->st);
-    void* ptrs[] = {c->P[0], c->P[1], c->H, c->F[0], c->F[1], c->F[2], c->rhs, c->coef,
-                    c->interior, c->hookP[0], c->hookP[1], c->iters, c->resid, c->flags, c->stats, c->u64,
-                    c->geo_centre, c->geo_face[0], c->geo_face[1], c->geo_face[2], c->geo_conn, c->mlp_p,
-                    c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->mlp_x, c->mlp_y, c->mlp_grad, c->adam_m, c->adam_v,
-                    c->mlp_idx, c->dloss, c->work.xh, c->work.tb, c->work.z1, c->work.h1, c->work.z2, c->work.h2,
-                    c->work.o, c->work.d_o, c->work.dh, c->work.dh1};
+    // the workspace buffers are carved from c->ws; the training buffers are
+    // allocated one by one
+    void* ptrs[] = {c->mlp_grad, c->adam_m, c->adam_v, c->mlp_idx, c->dloss, c->work.xh, c->work.tb,
+                    c->work.z1, c->work.h1, c->work.z2, c->work.h2, c->work.o, c->work.d_o, c->work.dh,
+                    c->work.dh1};
     for (void* p : ptrs)
         if (p) hipFree(p);
+    if (c->own_ws && c->ws) hipFree(c->ws);
 }
 
 int validate(const grim_config_t* g, std::string& why)
@@ -151,13 +165,105 @@ int validate(const grim_config_t* g, std::string& why)
     if (g->model == GRIM_EMHD && !(g->tau_R > 0 && g->chi > 0 && g->nu > 0))
         return why = "EMHD needs tau_R, chi, nu > 0", 1;
     if (!(g->tol > 0) || !(g->eps_fd > 0) || !(g->eps_bt >= 0)) return why = "bad tolerances", 1;
-    if (g->k_max < 0 || g->ls_max < 1) return why = "k_max >= 0 and ls_max >= 1 required", 1;
+    // the solver statistics pack per-wave sums into 21-bit fields
+    if (g->k_max < 0 || g->k_max > 100 || g->ls_max < 1 || g->ls_max > 64)
+        return why = "k_max in [0, 100] and ls_max in [1, 64] required", 1;
+    if (g->ls_safeguard != 0 && g->ls_safeguard != 1) return why = "ls_safeguard must be 0 or 1", 1;
+    if (g->external_workspace != 0 && g->external_workspace != 1)
+        return why = "external_workspace must be 0 or 1", 1;
     if (g->jac_precision != GRIM_JAC_F64 && g->jac_precision != GRIM_JAC_F32) return why = "bad jac_precision", 1;
     if (g->guess != GRIM_GUESS_PN && g->guess != GRIM_GUESS_MLP) return why = "bad guess", 1;
 
     const double zones = (double)n[0] * n[1] * n[2];
     if (zones > 2.0e9) return why = "too many zones", 1;
     return 0;
+}
+
+// Grid layout of a configuration (ghost layers on active directions only).
+Layout layout_of(const grim_config_t* cfg)
+{
+    Layout L{};
+    L.ndim = cfg->ndim;
+    const int n[3] = {cfg->n1, cfg->n2, cfg->n3};
+    for (int d = 0; d < 3; ++d) {
+        L.n[d] = n[d];
+        L.g[d] = d < cfg->ndim ? cfg->ng : 0;
+        L.N[d] = n[d] + 2 * L.g[d];
+        L.xs[d] = cfg->x_start[d];
+        L.dx[d] = d < cfg->ndim ? (cfg->x_end[d] - cfg->x_start[d]) / n[d] : 1.0;
+    }
+    L.cells = (long)L.N[0] * L.N[1] * L.N[2];
+    L.nz = (long)n[0] * n[1] * n[2];
+    return L;
+}
+
+constexpr int kNormBlocks = 256;  // partial sums of the normalisation kernel
+constexpr int kNormCols = grim::kMlpIn + grim::kMlpOut;
+
+// Lay every device buffer of a context out in one workspace, each on a
+// 256-byte boundary, and return its size.  With c and base set, the
+// context's pointers are set into base; with c null only the size is
+// computed.
+size_t carve(const grim_config_t* cfg, grim_ctx* c, char* base)
+{
+    const Layout L = layout_of(cfg);
+    const size_t nv = (size_t)cfg->model, cells = (size_t)L.cells, nz = (size_t)L.nz;
+    size_t off = 0;
+    auto take = [&](auto** p, size_t count) {
+        using T = std::remove_reference_t<decltype(**p)>;
+        off = (off + 255) & ~(size_t)255;
+        if (c && base) *p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+    };
+    grim_ctx dummy;
+    grim_ctx* t = c ? c : &dummy;
+    take(&t->P[0], nv * cells);
+    take(&t->P[1], nv * cells);
+    take(&t->H, nv * cells);
+    for (int d = 0; d < cfg->ndim; ++d) take(&t->F[d], nv * cells);
+    take(&t->rhs, nv * nz);
+    if (cfg->model == GRIM_EMHD) take(&t->coef, (size_t)grim::kEmhdCoef * nz);
+    take(&t->interior, nv * nz);
+    take(&t->hookP[0], nv * cells);
+    take(&t->hookP[1], nv * cells);
+    take(&t->iters, nz);
+    take(&t->resid, nz);
+    take(&t->flags, nz);
+    take(&t->stats, (size_t)grim::kStatCopies);
+    take(&t->u64, 4);
+    take(&t->nrm, (size_t)(kNormBlocks + 2) * kNormCols);
+    take(&t->mlp_p, (size_t)grim::kMlpParams);
+    take(&t->mlp_w[0], (size_t)grim::kMlpHidden * grim::kMlpIn);
+    take(&t->mlp_w[1], (size_t)grim::kMlpHidden * grim::kMlpHidden);
+    take(&t->mlp_w[2], (size_t)32 * grim::kMlpHidden);
+    take(&t->mlp_x, nz * grim::kMlpIn);
+    take(&t->mlp_y, nz * grim::kMlpOut);
+    if (cfg->metric == GRIM_MKS_KERR) {
+        const size_t s2 = (size_t)L.N[0] * L.N[1];
+        take(&t->geo_centre, grim::kGeoDoubles * s2);
+        for (int d = 0; d < 3; ++d) take(&t->geo_face[d], grim::kGeoDoubles * s2);
+        take(&t->geo_conn, 64 * s2);
+    }
+    return (off + 255) & ~(size_t)255;
+}
+
+// Carve the context's buffers from its workspace, clear the state buffers
+// and build the metric tables (a1); synchronises.
+int init_workspace(grim_ctx* c, char* base, size_t bytes)
+{
+    c->ws = base;
+    c->ws_bytes = bytes;
+    c->bytes += bytes;
+    carve(&c->cfg, c, base);
+    const size_t nv = (size_t)c->nvar, cells = (size_t)c->L.cells;
+    double* zero[] = {c->P[0], c->P[1], c->H, c->F[0], c->F[1], c->F[2], c->hookP[0], c->hookP[1]};
+    for (double* p : zero)
+        if (p) HIP_TRY(c, hipMemsetAsync(p, 0, sizeof(double) * nv * cells, c->st));
+    if (c->cfg.metric == GRIM_MKS_KERR)
+        HIP_TRY(c, grim::build_geometry(c->L, c->cfg.spin_a, c->cfg.mks_h, c->geo_centre, c->geo_face, c->geo_conn,
+                                        c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
 }
 
 // Whether stage solves compute the right-hand side inside the Newton kernel.
@@ -204,6 +310,7 @@ NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
     a.eps_bt = c->cfg.eps_bt;
     a.k_max = c->cfg.k_max;
     a.ls_max = c->cfg.ls_max;
+    a.ls_safeguard = c->cfg.ls_safeguard;
     a.iters = c->iters;
     a.resid = c->resid;
     a.flags = c->flags;
@@ -304,14 +411,6 @@ int enqueue_step(grim_ctx* c, int from, double dt, hipStream_t st, Collect* col 
     return enqueue_stage(c, A, c->H, dt, B, 1, st, col);
 }
 
-int ensure_mlp_zone_buffers(grim_ctx* c)
-{
-    int rc = GRIM_OK;
-    if (!c->mlp_x) rc = dalloc(c, &c->mlp_x, (size_t)c->L.nz * grim::kMlpIn);
-    if (!rc && !c->mlp_y) rc = dalloc(c, &c->mlp_y, (size_t)c->L.nz * grim::kMlpOut);
-    return rc;
-}
-
 int ensure_mlp_train_buffers(grim_ctx* c, int cap)
 {
     grim::MlpWork& w = c->work;
@@ -337,17 +436,6 @@ int ensure_mlp_train_buffers(grim_ctx* c, int cap)
     return rc;
 }
 
-int ensure_hook_buffers(grim_ctx* c)
-{
-    for (int i = 0; i < 2; ++i)
-        if (!c->hookP[i]) {
-            int rc = dalloc(c, &c->hookP[i], (size_t)c->nvar * c->L.cells);
-            if (rc) return rc;
-            HIP_TRY(c, hipMemsetAsync(c->hookP[i], 0, sizeof(double) * c->nvar * c->L.cells, c->st));
-        }
-    return GRIM_OK;
-}
-
 // Stage the hook inputs P_n (interior) and P^E (interior) into ghosted
 // buffers and run the explicit stage.
 int hook_setup(grim_ctx* c, const double* Pn, const double* PE, double dtp, StageArgs* out, double* dbg_divF,
@@ -355,8 +443,6 @@ int hook_setup(grim_ctx* c, const double* Pn, const double* PE, double dtp, Stag
 {
     if (!Pn || !PE) return fail(c, GRIM_E_INVALID_ARG, "null input pointer");
     if (!(dtp > 0.0) || !std::isfinite(dtp)) return fail(c, GRIM_E_INVALID_ARG, "dt' must be positive");
-    int rc = ensure_hook_buffers(c);
-    if (rc) return rc;
     HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, Pn, 0, c->hookP[0], 1, c->st));
     HIP_TRY(c, grim::launch_copy_interior(c->L, c->nvar, PE, 0, c->hookP[1], 1, c->st));
     const int bc[3] = {c->cfg.bc[0], c->cfg.bc[1], c->cfg.bc[2]};
@@ -367,6 +453,34 @@ int hook_setup(grim_ctx* c, const double* Pn, const double* PE, double dtp, Stag
     s.dbg_sp = dbg_sp;
     HIP_TRY(c, grim::launch_explicit_stage(s, c->nvar, c->cfg.metric, c->st));
     *out = s;
+    return GRIM_OK;
+}
+
+// Sum the statistics copies on the host into stats; `per_stage` stages of
+// every zone were accumulated into each stage slot.  Synchronises.
+int read_stats(grim_ctx* c, int per_stage, grim_stats_t* stats)
+{
+    std::vector<DevStats> copies(grim::kStatCopies);
+    HIP_TRY(c, hipMemcpyAsync(copies.data(), c->stats, sizeof(DevStats) * grim::kStatCopies, hipMemcpyDeviceToHost,
+                              c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    const DevStats d = grim::sum_stats(copies.data(), grim::kStatCopies);
+    const double zs = (double)c->L.nz * (double)per_stage;
+    stats->mean_iters[0] = (double)d.iters[0] / zs;
+    stats->mean_iters[1] = (double)d.iters[1] / zs;
+    stats->max_iters = (int32_t)d.max_iters;
+    stats->pad = 0;
+    stats->n_fail = (int64_t)d.n_fail;
+    stats->n_ls_exhausted = (int64_t)d.n_ls;
+    stats->n_unphysical = (int64_t)d.n_unphys;
+    double mr;
+    std::memcpy(&mr, &d.max_resid_bits, sizeof(mr));
+    stats->max_resid = mr;
+    stats->zone_stages = (int64_t)d.zone_stages;
+    stats->n_resid_calls = (int64_t)d.resid_calls;
+    stats->n_fallback = (int64_t)d.n_fallback;
+    stats->n_f64_retry = (int64_t)d.n_retry;
+    stats->n_backtracks = (int64_t)d.n_bt;
     return GRIM_OK;
 }
 
@@ -414,18 +528,7 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
             c->cus = 0;
     }
     c->nvar = cfg->model;
-    Layout& L = c->L;
-    L.ndim = cfg->ndim;
-    const int n[3] = {cfg->n1, cfg->n2, cfg->n3};
-    for (int d = 0; d < 3; ++d) {
-        L.n[d] = n[d];
-        L.g[d] = d < cfg->ndim ? cfg->ng : 0;
-        L.N[d] = n[d] + 2 * L.g[d];
-        L.xs[d] = cfg->x_start[d];
-        L.dx[d] = d < cfg->ndim ? (cfg->x_end[d] - cfg->x_start[d]) / n[d] : 1.0;
-    }
-    L.cells = (long)L.N[0] * L.N[1] * L.N[2];
-    L.nz = (long)n[0] * n[1] * n[2];
+    c->L = layout_of(cfg);
     Phys& ph = c->ph;
     ph.gam = cfg->gamma;
     ph.gm1 = cfg->gamma - 1.0;
@@ -439,53 +542,56 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
         ph.vq2 = (cfg->gamma - 1.0) * cfg->chi / cfg->tau_R;
         ph.vd2 = 4.0 * cfg->nu / (3.0 * cfg->tau_R);
     }
-    const size_t nv = (size_t)c->nvar;
-    int rc = GRIM_OK;
-    for (int i = 0; i < 2 && !rc; ++i) rc = dalloc(c, &c->P[i], nv * L.cells);
-    if (!rc) rc = dalloc(c, &c->H, nv * L.cells);
-    for (int d = 0; d < cfg->ndim && !rc; ++d) rc = dalloc(c, &c->F[d], nv * L.cells);
-    if (!rc) rc = dalloc(c, &c->rhs, nv * L.nz);
-    if (!rc && c->nvar == GRIM_EMHD) rc = dalloc(c, &c->coef, (size_t)grim::kEmhdCoef * L.nz);
-    if (!rc) rc = dalloc(c, &c->interior, nv * L.nz);
-    if (!rc) rc = dalloc(c, &c->iters, (size_t)L.nz);
-    if (!rc) rc = dalloc(c, &c->resid, (size_t)L.nz);
-    if (!rc) rc = dalloc(c, &c->flags, (size_t)L.nz);
-    if (!rc) rc = dalloc(c, &c->stats, (size_t)grim::kStatCopies);
-    if (!rc) rc = dalloc(c, &c->u64, 4);
-    if (!rc) rc = dalloc(c, &c->mlp_p, (size_t)grim::kMlpParams);
-    if (!rc) rc = dalloc(c, &c->mlp_w[0], (size_t)grim::kMlpHidden * grim::kMlpIn);
-    if (!rc) rc = dalloc(c, &c->mlp_w[1], (size_t)grim::kMlpHidden * grim::kMlpHidden);
-    if (!rc) rc = dalloc(c, &c->mlp_w[2], (size_t)32 * grim::kMlpHidden);
-    if (!rc && cfg->guess == GRIM_GUESS_MLP) rc = ensure_mlp_zone_buffers(c);
-    if (!rc && cfg->metric == GRIM_MKS_KERR) {
-        const size_t s = (size_t)L.N[0] * L.N[1];
-        rc = dalloc(c, &c->geo_centre, grim::kGeoDoubles * s);
-        for (int d = 0; d < 3 && !rc; ++d) rc = dalloc(c, &c->geo_face[d], grim::kGeoDoubles * s);
-        if (!rc) rc = dalloc(c, &c->geo_conn, 64 * s);
-    }
-    if (rc) {
-        g_last_error = c->err;
-        release(c);
-        delete c;
-        return rc;
-    }
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMemsetAsync(c->P[i], 0, sizeof(double) * nv * L.cells, c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->H, 0, sizeof(double) * nv * L.cells, c->st);
-    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
-        if (c->F[d]) e = hipMemsetAsync(c->F[d], 0, sizeof(double) * nv * L.cells, c->st);
-    }
-    if (e == hipSuccess && cfg->metric == GRIM_MKS_KERR)
-        e = grim::build_geometry(L, cfg->spin_a, cfg->mks_h, c->geo_centre, c->geo_face, c->geo_conn, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    if (e != hipSuccess) {
-        g_last_error = std::string("device initialisation: ") + hipGetErrorString(e);
-        release(c);
-        delete c;
-        return GRIM_E_HIP;
+    if (!cfg->external_workspace) {
+        // the whole workspace in one allocation
+        const size_t bytes = carve(cfg, nullptr, nullptr);
+        char* base = nullptr;
+        hipError_t e = hipMalloc((void**)&base, bytes);
+        int rc = GRIM_OK;
+        if (e != hipSuccess) {
+            rc = e == hipErrorOutOfMemory ? GRIM_E_OOM : GRIM_E_HIP;
+            c->err = std::string("hipMalloc(") + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
+        } else {
+            c->own_ws = true;
+            rc = init_workspace(c, base, bytes);
+            if (rc) c->err = "device initialisation: " + c->err;
+        }
+        if (rc) {
+            g_last_error = c->err;
+            release(c);
+            delete c;
+            return rc;
+        }
     }
     *out = c;
     return GRIM_OK;
+}
+
+size_t grim_workspace_bytes(const grim_config_t* cfg)
+{
+    if (!cfg) {
+        fail(nullptr, GRIM_E_INVALID_ARG, "null config");
+        return 0;
+    }
+    std::string why;
+    if (validate(cfg, why)) {
+        fail(nullptr, GRIM_E_INVALID_ARG, "invalid config: " + why);
+        return 0;
+    }
+    return carve(cfg, nullptr, nullptr);
+}
+
+int grim_bind_workspace(grim_ctx_t* c, void* dev_ptr, size_t bytes)
+{
+    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (!c->cfg.external_workspace) return fail(c, GRIM_E_STATE, "the context allocated its own workspace");
+    if (c->ws) return fail(c, GRIM_E_STATE, "a workspace is already bound");
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255u)) return fail(c, GRIM_E_INVALID_ARG, "null or not 256-byte aligned");
+    const size_t need = carve(&c->cfg, nullptr, nullptr);
+    if (bytes < need)
+        return fail(c, GRIM_E_INVALID_ARG,
+                    "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(need) + " bytes");
+    return init_workspace(c, (char*)dev_ptr, need);
 }
 
 int grim_destroy(grim_ctx_t* ctx)
@@ -499,7 +605,7 @@ int grim_destroy(grim_ctx_t* ctx)
 
 int grim_set_prims(grim_ctx_t* c, const double* P, int on_device)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!P) return fail(c, GRIM_E_INVALID_ARG, "null P");
     const size_t bytes = sizeof(double) * c->nvar * c->L.nz;
     const double* src = P;
@@ -516,7 +622,7 @@ int grim_set_prims(grim_ctx_t* c, const double* P, int on_device)
 
 int grim_get_prims(grim_ctx_t* c, double* P, int on_device)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!P) return fail(c, GRIM_E_INVALID_ARG, "null P");
     const size_t bytes = sizeof(double) * c->nvar * c->L.nz;
     if (on_device) {
@@ -531,7 +637,7 @@ int grim_get_prims(grim_ctx_t* c, double* P, int on_device)
 
 int grim_cfl_dt(grim_ctx_t* c, double cfl, double* dt)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!dt || !(cfl > 0.0)) return fail(c, GRIM_E_INVALID_ARG, "cfl must be positive and dt non-null");
     const unsigned long long init = 0x7FEFFFFFFFFFFFFFull;  // largest finite double
     HIP_TRY(c, hipMemcpyAsync(c->u64, &init, sizeof(init), hipMemcpyHostToDevice, c->st));
@@ -553,7 +659,7 @@ constexpr int kGraphSteps = 16;
 
 int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* stats)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return fail(c, GRIM_E_INVALID_ARG, "bad dt or nsteps");
     if (c->cfg.guess == GRIM_GUESS_MLP && !c->mlp_set)
         return fail(c, GRIM_E_STATE, "learned guess requested but no network weights were set");
@@ -598,35 +704,14 @@ int grim_run(grim_ctx_t* c, double dt, int nsteps, int use_graph, grim_stats_t* 
             c->cur = 1 - c->cur;
         }
     }
-    if (stats) {
-        std::vector<DevStats> copies(grim::kStatCopies);
-        HIP_TRY(c, hipMemcpyAsync(copies.data(), c->stats, sizeof(DevStats) * grim::kStatCopies,
-                                  hipMemcpyDeviceToHost, c->st));
-        HIP_TRY(c, hipStreamSynchronize(c->st));
-        const DevStats d = grim::sum_stats(copies.data(), grim::kStatCopies);
-        const double per_stage = (double)c->L.nz * (double)(nsteps > 0 ? nsteps : 1);
-        stats->mean_iters[0] = (double)d.iters[0] / per_stage;
-        stats->mean_iters[1] = (double)d.iters[1] / per_stage;
-        stats->max_iters = (int32_t)d.max_iters;
-        stats->pad = 0;
-        stats->n_fail = (int64_t)d.n_fail;
-        stats->n_ls_exhausted = (int64_t)d.n_ls;
-        stats->n_unphysical = (int64_t)d.n_unphys;
-        double mr;
-        std::memcpy(&mr, &d.max_resid_bits, sizeof(mr));
-        stats->max_resid = mr;
-        stats->zone_stages = (int64_t)d.zone_stages;
-        stats->n_resid_calls = (int64_t)d.resid_calls;
-        stats->n_fallback = (int64_t)d.n_fallback;
-        stats->n_f64_retry = (int64_t)d.n_retry;
-    }
+    if (stats) return read_stats(c, nsteps > 0 ? nsteps : 1, stats);
     return GRIM_OK;
 }
 
 int grim_residual(grim_ctx_t* c, const double* Pn, const double* PE, double dtp, const double* P, double* R,
                   double* rnorm)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!P || !R) return fail(c, GRIM_E_INVALID_ARG, "null P or R");
     StageArgs s;
     int rc = hook_setup(c, Pn, PE, dtp, &s, nullptr, nullptr, nullptr);
@@ -637,9 +722,10 @@ int grim_residual(grim_ctx_t* c, const double* Pn, const double* PE, double dtp,
 }
 
 int grim_stage_solve(grim_ctx_t* c, const double* Pn, const double* PE, double dtp, const double* guess,
-                     double* P_out, int32_t* iters, double* resid, uint8_t* flags)
+                     double* P_out, int32_t* iters, double* resid, uint8_t* flags, int32_t* backtracks,
+                     grim_stats_t* stats)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!P_out) return fail(c, GRIM_E_INVALID_ARG, "null P_out");
     StageArgs s;
     int rc = hook_setup(c, Pn, PE, dtp, &s, nullptr, nullptr, nullptr);
@@ -655,14 +741,16 @@ int grim_stage_solve(grim_ctx_t* c, const double* Pn, const double* PE, double d
     if (iters) n.iters = iters;
     if (resid) n.resid = resid;
     if (flags) n.flags = flags;
+    n.backtracks = backtracks;
     HIP_TRY(c, grim::launch_newton(n, c->nvar, c->cfg.metric, c->cfg.jac_precision, c->st));
+    if (stats) return read_stats(c, 1, stats);
     HIP_TRY(c, hipStreamSynchronize(c->st));
     return GRIM_OK;
 }
 
 int grim_explicit(grim_ctx_t* c, const double* PE, double* divF, double* srcE, double* emhd_sp)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!divF || !srcE) return fail(c, GRIM_E_INVALID_ARG, "null divF or srcE");
     StageArgs s;
     int rc = hook_setup(c, PE, PE, 1.0, &s, divF, srcE, emhd_sp);
@@ -673,7 +761,7 @@ int grim_explicit(grim_ctx_t* c, const double* PE, double* divF, double* srcE, d
 
 int grim_get_zone_results(grim_ctx_t* c, uint8_t* flags, int32_t* iters, int on_device)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (flags) HIP_TRY(c, hipMemcpyAsync(flags, c->flags, (size_t)c->L.nz, k, c->st));
     if (iters) HIP_TRY(c, hipMemcpyAsync(iters, c->iters, sizeof(int32_t) * c->L.nz, k, c->st));
@@ -712,7 +800,7 @@ int grim_kernel_times(grim_ctx_t* c, double* ms, int64_t* launches, int n)
 
 int grim_mlp_set_weights(grim_ctx_t* c, const float* w, size_t n)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!w || n != (size_t)grim::kMlpParams) return fail(c, GRIM_E_INVALID_ARG, "need GRIM_MLP_PARAMS values");
     HIP_TRY(c, hipMemcpyAsync(c->mlp_p, w, sizeof(float) * n, hipMemcpyHostToDevice, c->st));
     HIP_TRY(c, grim::mlp_pack(c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], c->st));
@@ -723,7 +811,7 @@ int grim_mlp_set_weights(grim_ctx_t* c, const float* w, size_t n)
 
 int grim_mlp_get_weights(grim_ctx_t* c, float* w, size_t n)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!w || n != (size_t)grim::kMlpParams) return fail(c, GRIM_E_INVALID_ARG, "need GRIM_MLP_PARAMS values");
     if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
     HIP_TRY(c, hipMemcpyAsync(w, c->mlp_p, sizeof(float) * n, hipMemcpyDeviceToHost, c->st));
@@ -733,7 +821,7 @@ int grim_mlp_get_weights(grim_ctx_t* c, float* w, size_t n)
 
 int grim_mlp_forward(grim_ctx_t* c, const float* X, int64_t n, float* Y)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!X || !Y || n < 0) return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
     if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
     HIP_TRY(c, grim::mlp_infer(X, (long)n, c->mlp_p, c->mlp_w[0], c->mlp_w[1], c->mlp_w[2], Y, c->st));
@@ -743,7 +831,7 @@ int grim_mlp_forward(grim_ctx_t* c, const float* X, int64_t n, float* Y)
 
 int grim_mlp_backward(grim_ctx_t* c, const float* X, const float* dY, int64_t n, float* dW)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!X || !dY || !dW || n <= 0) return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
     if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
     const int chunk = 4096;
@@ -762,7 +850,7 @@ int grim_mlp_backward(grim_ctx_t* c, const float* X, const float* dY, int64_t n,
 int grim_mlp_train(grim_ctx_t* c, const float* X, const float* T, int64_t n, const grim_train_cfg_t* cfg,
                    double* loss_hist)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!X || !T || !cfg || n <= 0 || cfg->epochs < 0 || cfg->batch <= 0 || cfg->n_used <= 0 ||
         cfg->n_used > grim::kMlpOut || !(cfg->lr > 0))
         return fail(c, GRIM_E_INVALID_ARG, "bad training arguments");
@@ -806,14 +894,34 @@ int grim_mlp_train(grim_ctx_t* c, const float* X, const float* T, int64_t n, con
     return GRIM_OK;
 }
 
+int grim_mlp_normalisation(grim_ctx_t* c, const float* X, const float* T, int64_t n, int n_used, double* x_mean,
+                           double* x_istd, double* y_scale)
+{
+    if (int rc_ = usable(c)) return rc_;
+    if (!X || !T || !x_mean || !x_istd || !y_scale || n < 2 || n_used < 1 || n_used > grim::kMlpOut)
+        return fail(c, GRIM_E_INVALID_ARG, "bad arguments (n >= 2 and n_used in [1, 16] required)");
+    HIP_TRY(c, grim::mlp_norm_stats(X, T, (long)n, c->nrm, kNormBlocks, c->st));
+    double mv[2 * kNormCols];
+    HIP_TRY(c, hipMemcpyAsync(mv, c->nrm + (size_t)kNormBlocks * kNormCols, sizeof(mv), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    const double* mean = mv;
+    const double* var = mv + kNormCols;
+    for (int i = 0; i < grim::kMlpIn; ++i) {
+        x_mean[i] = mean[i];
+        x_istd[i] = var[i] > 0.0 ? 1.0 / std::sqrt(var[i]) : 0.0;
+    }
+    for (int i = 0; i < grim::kMlpOut; ++i)
+        y_scale[i] = (i < n_used && var[grim::kMlpIn + i] > 0.0) ? std::sqrt(var[grim::kMlpIn + i]) : 0.0;
+    return GRIM_OK;
+}
+
 int grim_collect_pairs(grim_ctx_t* c, double dt, int nsteps, int stride, float* X, float* T, int64_t cap,
                        int64_t* count)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!X || !T || !count || stride < 1 || cap < 0 || nsteps < 0 || !(dt > 0.0))
         return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
-    int rc = ensure_mlp_zone_buffers(c);
-    if (rc) return rc;
+    int rc = GRIM_OK;
     Collect col{stride, 0, X, T, (long)cap, 0};
     for (int s = 0; s < nsteps; ++s) {
         rc = enqueue_step(c, c->cur, dt, c->st, &col);
@@ -827,7 +935,7 @@ int grim_collect_pairs(grim_ctx_t* c, double dt, int nsteps, int stride, float* 
 
 int grim_math_probe(grim_ctx_t* c, const double* x, double* out, size_t n)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (n > 0 && (!x || !out)) return fail(c, GRIM_E_INVALID_ARG, "null pointer");
     HIP_TRY(c, grim::launch_math_probe(x, out, n, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
@@ -836,7 +944,7 @@ int grim_math_probe(grim_ctx_t* c, const double* x, double* out, size_t n)
 
 int grim_stream_add(grim_ctx_t* c, const double* a, const double* b, double* cc, size_t n)
 {
-    if (!c) return fail(nullptr, GRIM_E_INVALID_ARG, "null context");
+    if (int rc_ = usable(c)) return rc_;
     if (!a || !b || !cc) return fail(c, GRIM_E_INVALID_ARG, "null pointer");
     HIP_TRY(c, grim::launch_stream_add(a, b, cc, n, c->st));
     return GRIM_OK;

@@ -70,7 +70,7 @@ __host__ __device__ inline unsigned plane_blocks(long points, unsigned planes, u
 constexpr int kStatCopies = 256;
 struct alignas(128) DevStats {
     unsigned long long iters[2];
-    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback, n_retry;
+    unsigned long long n_fail, n_ls, n_unphys, zone_stages, resid_calls, n_fallback, n_retry, n_bt;
     unsigned long long max_resid_bits;
     unsigned int max_iters;
     unsigned int pad;
@@ -90,6 +90,7 @@ inline DevStats sum_stats(const DevStats* s, int n)
         d.resid_calls += s[i].resid_calls;
         d.n_fallback += s[i].n_fallback;
         d.n_retry += s[i].n_retry;
+        d.n_bt += s[i].n_bt;
         d.max_resid_bits = s[i].max_resid_bits > d.max_resid_bits ? s[i].max_resid_bits : d.max_resid_bits;
         d.max_iters = s[i].max_iters > d.max_iters ? s[i].max_iters : d.max_iters;
     }
@@ -163,6 +164,8 @@ struct NewtonArgs {
     const float* mlp_y;    // if set: network output per zone [nz][kMlpOut] -> candidate guess
     double tol, eps, eps_bt;
     int k_max, ls_max;
+    int ls_safeguard;      // 1: each new lambda kept in [0.1, 0.5] of the previous
+    int32_t* backtracks;   // if set: rejected line-search trials per zone
     // 0: one solve; 1: FP32 pass that marks failed zones kFlagRetry instead
     // of counting them; 2: FP64 solve from P_n of the marked zones only
     int pass;
@@ -212,6 +215,10 @@ hipError_t mlp_batch_grad(const MlpWork& w, const float* X, const float* T, cons
                           double* loss, hipStream_t st);
 hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                     int step, hipStream_t st);
+// Means and unbiased variances of the 32 input and 16 target columns of n
+// training pairs, into work[nblocks * 48 ..] (means) and the 48 doubles after
+// them (variances); work holds (nblocks + 2) * 48 doubles.
+hipError_t mlp_norm_stats(const float* X, const float* T, long n, double* work, int nblocks, hipStream_t st);
 hipError_t build_geometry(const Layout& L, double spin, double h, double* centre, double* face[3], double* conn,
                           hipStream_t st);
 

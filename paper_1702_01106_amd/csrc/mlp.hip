@@ -349,6 +349,45 @@ void gemm(const float* A, int lda, int ta, const float* B, int ldb, int tb, floa
                        N, K, acc);
 }
 
+// Column statistics of the training pairs (the network's normalisation):
+// 48 columns, X's 32 then T's 16.  Block b of nb sums rows b, b + nb, ... of
+// each column in FP64 (mode 0: x; mode 1: (x - mean)^2), its four row lanes
+// are combined in a fixed order, and part[b][col] holds the block's sum, so
+// the result does not depend on timing.
+constexpr int kNormCols = DI + DO, kNormLanes = 4;
+__global__ __launch_bounds__(kNormCols* kNormLanes) void k_norm_partial(const float* __restrict__ X,
+                                                                       const float* __restrict__ T, long n,
+                                                                       const double* __restrict__ mean, int mode,
+                                                                       double* __restrict__ part)
+{
+    __shared__ double red[kNormLanes][kNormCols];
+    const int col = threadIdx.x % kNormCols, lane = threadIdx.x / kNormCols;
+    const double m = mode ? mean[col] : 0.0;
+    double acc = 0.0;
+    for (long r = (long)blockIdx.x * kNormLanes + lane; r < n; r += (long)gridDim.x * kNormLanes) {
+        const double x = col < DI ? (double)X[r * DI + col] : (double)T[r * DO + col - DI];
+        const double d = x - m;
+        acc += mode ? d * d : x;
+    }
+    red[lane][col] = acc;
+    __syncthreads();
+    if (lane == 0) {
+        double t = 0.0;
+        for (int l = 0; l < kNormLanes; ++l) t += red[l][col];
+        part[(long)blockIdx.x * kNormCols + col] = t;
+    }
+}
+
+// out[col] = (sum over blocks of part[b][col], in block order) * scale
+__global__ void k_norm_final(const double* __restrict__ part, int nb, double scale, double* __restrict__ out)
+{
+    const int col = threadIdx.x;
+    if (col >= kNormCols) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[(long)b * kNormCols + col];
+    out[col] = t * scale;
+}
+
 }  // namespace
 
 hipError_t mlp_pack(const float* params, unsigned short* w1t, unsigned short* w2t, unsigned short* w3t, hipStream_t st)
@@ -409,6 +448,19 @@ hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int n, float l
 {
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3(nb(n, 256)), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+
+hipError_t mlp_norm_stats(const float* X, const float* T, long n, double* work, int nblocks, hipStream_t st)
+{
+    // work: nblocks x 48 partial sums, then the 48 means and 48 variances
+    double* mean = work + (long)nblocks * kNormCols;
+    double* var = mean + kNormCols;
+    hipLaunchKernelGGL(k_norm_partial, dim3(nblocks), dim3(kNormCols * kNormLanes), 0, st, X, T, n, mean, 0, work);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, 1.0 / (double)n, mean);
+    hipLaunchKernelGGL(k_norm_partial, dim3(nblocks), dim3(kNormCols * kNormLanes), 0, st, X, T, n, mean, 1, work);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, 1.0 / (double)(n - 1), var);
     return hipGetLastError();
 }
 

@@ -5,10 +5,12 @@
 //   perturbation rule of Sec. 3.1 (a9): column j = (R(P_eps,j) - R(P))/h_j,
 //   h_j = P_eps,j - P_j.  Dense LU with partial pivoting (a10): row swaps are
 //   branch-free selects so J never leaves registers.  Quadratic backtracking
-//   line search (a11, Sec. 3.2), each new lambda kept in [0.1, 0.5] of the
-//   previous one.  Converged lanes go idle; the wave leaves
-//   the loop when every lane has (a12).  Statistics are reduced across the
-//   wave with shuffles and accumulated with one atomic per wave (a13).
+//   line search (a11, Sec. 3.2): each new lambda is the minimiser of the
+//   quadratic model, or with the safeguard option that minimiser kept in
+//   [0.1, 0.5] of the previous lambda.  Converged lanes go idle; the wave
+//   leaves the loop when every lane has (a12).  Statistics are reduced across
+//   the wave with DPP moves and ballots and accumulated with one atomic per
+//   wave and counter (a13).
 //
 // JT selects the precision of the difference quotients, the stored Jacobian
 // and the LU: double (the plain method) or float (mixed precision; the
@@ -265,7 +267,7 @@ struct ZoneSolve {
     double P[NV], R[NV];
     double r, nscale, fB;
     long z, cell;
-    int k, iters, ncalls, fallback;
+    int k, iters, ncalls, nbt, fallback;
     bool from_net;
     uint8_t fl;
 };
@@ -297,6 +299,7 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
     s.k = 0;
     s.iters = 0;
     s.ncalls = 0;
+    s.nbt = 0;
     s.fallback = 0;
     s.from_net = false;
     s.fl = 0;
@@ -395,13 +398,15 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
                         accepted = true;
                         break;
                     }
-                    // minimiser of the quadratic model f(0) - 2 f(0) lam + c lam^2,
-                    // kept within [0.1, 0.5] of the previous lambda
+                    // minimiser of the quadratic model f(0) - 2 f(0) lam + c lam^2
+                    // through f(lam) (eq. linesearch_residual), optionally kept
+                    // within [0.1, 0.5] of the previous lambda
                     const double ln = f0 * lam * lam / (rt * rt + (2.0 * lam - 1.0) * f0);
-                    lam = fmin(fmax(ln, 0.1 * lam), 0.5 * lam);
+                    lam = a.ls_safeguard ? fmin(fmax(ln, 0.1 * lam), 0.5 * lam) : ln;
                 } else {
                     lam *= 0.5;
                 }
+                ++s.nbt;  // a rejected trial
             }
             ++s.iters;
             ++s.k;
@@ -442,7 +447,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
 
 // Per-lane accumulators of the statistics over the zones a lane finishes.
 struct LaneStats {
-    int iters = 0, nc = 0;  // Newton iterations, residual evaluations
+    int iters = 0, nc = 0, nbt = 0;  // Newton iterations, residual evaluations, rejected trials
     bool nf = false, nl = false, nu = false, na = false, nfb = false, nrt = false;
     unsigned long long rb = 0;  // bits of the final residual (ordered like the value)
 };
@@ -481,6 +486,12 @@ __device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>&
         else
             a.iters[z] = s.iters;
     }
+    if (a.backtracks) {
+        if (retry)
+            a.backtracks[z] += s.nbt;
+        else
+            a.backtracks[z] = s.nbt;
+    }
     if (a.resid) a.resid[z] = s.r;
     if (a.flags) a.flags[z] = s.fl;
     // a zone marked for the FP64 retry contributes only its work (iterations,
@@ -488,6 +499,7 @@ __device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>&
     const bool final_ = !(a.pass == 1 && (s.fl & kFlagRetry));
     ls.iters = s.iters;
     ls.nc = s.ncalls;
+    ls.nbt = s.nbt;
     ls.nfb = s.fallback != 0;
     ls.na = !retry;
     ls.nrt = retry;
@@ -502,11 +514,15 @@ __device__ __forceinline__ void zs_finish(const NewtonArgs& a, ZoneSolve<NV, G>&
 }
 
 // Wave reduction of the lane statistics, one atomic per wave and counter:
-// the 0/1 counters are popcounts of ballots; the iteration and residual-call
-// counts share one 64-bit sum (each half stays below 2^32).
+// the 0/1 counters are popcounts of ballots; the iteration, residual-call and
+// rejected-trial counts share one 64-bit sum in 21-bit fields (the host caps
+// k_max at 100 and ls_max at 64, so a wave's sums stay below 2^20).
+constexpr int kPack = 21;
+constexpr unsigned long long kPackMask = (1ull << kPack) - 1;
 __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats& ls)
 {
-    const unsigned long long both = wave_sumu64(((unsigned long long)(unsigned)ls.nc << 32) | (unsigned)ls.iters);
+    const unsigned long long all = wave_sumu64(((unsigned long long)(unsigned)ls.nbt << (2 * kPack)) |
+                                               ((unsigned long long)(unsigned)ls.nc << kPack) | (unsigned)ls.iters);
     const int mit = wave_max(ls.iters);
     const unsigned long long rb = wave_maxu64(ls.rb);
     const unsigned long long nf = __popcll(__ballot(ls.nf)), nl = __popcll(__ballot(ls.nl)),
@@ -514,14 +530,16 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
                              nfb = __popcll(__ballot(ls.nfb)), nrt = __popcll(__ballot(ls.nrt));
     DevStats* ds = a.stats + (blockIdx.x & (kStatCopies - 1));
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicAdd(&ds->iters[a.stage], both & 0xFFFFFFFFull);
+        atomicAdd(&ds->iters[a.stage], all & kPackMask);
         atomicMax(&ds->max_iters, (unsigned)mit);
         if (nf > 0) atomicAdd(&ds->n_fail, nf);
         if (nl > 0) atomicAdd(&ds->n_ls, nl);
         if (nu > 0) atomicAdd(&ds->n_unphys, nu);
         if (na > 0) atomicAdd(&ds->zone_stages, na);
         if (nrt > 0) atomicAdd(&ds->n_retry, nrt);
-        atomicAdd(&ds->resid_calls, both >> 32);
+        atomicAdd(&ds->resid_calls, (all >> kPack) & kPackMask);
+        const unsigned long long nbt = all >> (2 * kPack);
+        if (nbt > 0) atomicAdd(&ds->n_bt, nbt);
         if (nfb > 0) atomicAdd(&ds->n_fallback, nfb);
         atomicMax(&ds->max_resid_bits, rb);
     }
@@ -808,12 +826,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             // FP64 Jacobian in the same lane (the two-pass kernels do this in
             // a second launch); iterations and residual calls of both count
             if (s.fl & (1 | 4 | 16)) {
-                const int it = s.iters, nc = s.ncalls;
+                const int it = s.iters, nc = s.ncalls, nb = s.nbt;
                 zs_begin<NV, GeoMink, ND>(a, z, nullptr, nullptr, s, &in);
                 while (!zs_step<NV, GeoMink, double>(a, s)) {
                 }
                 s.iters += it;
                 s.ncalls += nc;
+                s.nbt += nb;
                 s.fl |= kFlagRetry;
                 retried = true;
             }

@@ -38,6 +38,7 @@ class grim_config_t(C.Structure):
         ("k_max", C.c_int), ("ls_max", C.c_int),
         ("jac_precision", C.c_int), ("guess", C.c_int),
         ("floors", C.c_int), ("rho_floor", C.c_double), ("u_floor", C.c_double),
+        ("ls_safeguard", C.c_int), ("external_workspace", C.c_int),
     ]
 
 
@@ -46,7 +47,7 @@ class grim_stats_t(C.Structure):
         ("mean_iters", C.c_double * 2), ("max_iters", C.c_int32), ("pad", C.c_int32),
         ("n_fail", C.c_int64), ("n_ls_exhausted", C.c_int64), ("n_unphysical", C.c_int64),
         ("max_resid", C.c_double), ("zone_stages", C.c_int64), ("n_resid_calls", C.c_int64),
-        ("n_fallback", C.c_int64), ("n_f64_retry", C.c_int64),
+        ("n_fallback", C.c_int64), ("n_f64_retry", C.c_int64), ("n_backtracks", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -61,6 +62,7 @@ class grim_stats_t(C.Structure):
             "n_resid_calls": int(self.n_resid_calls),
             "n_fallback": int(self.n_fallback),
             "n_f64_retry": int(self.n_f64_retry),
+            "n_backtracks": int(self.n_backtracks),
         }
 
 
@@ -94,12 +96,15 @@ def load():
     L.grim_last_global_error.restype = C.c_char_p
     L.grim_device_bytes.argtypes = [_VP]
     L.grim_device_bytes.restype = C.c_size_t
+    L.grim_workspace_bytes.argtypes = [C.POINTER(grim_config_t)]
+    L.grim_workspace_bytes.restype = C.c_size_t
+    L.grim_bind_workspace.argtypes = [_VP, _VP, C.c_size_t]
     L.grim_set_prims.argtypes = [_VP, _VP, C.c_int]
     L.grim_get_prims.argtypes = [_VP, _VP, C.c_int]
     L.grim_cfl_dt.argtypes = [_VP, _D, C.POINTER(_D)]
     L.grim_run.argtypes = [_VP, _D, C.c_int, C.c_int, C.POINTER(grim_stats_t)]
     L.grim_residual.argtypes = [_VP, _VP, _VP, _D, _VP, _VP, _VP]
-    L.grim_stage_solve.argtypes = [_VP, _VP, _VP, _D, _VP, _VP, _VP, _VP, _VP]
+    L.grim_stage_solve.argtypes = [_VP, _VP, _VP, _D, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(grim_stats_t)]
     L.grim_explicit.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.grim_get_zone_results.argtypes = [_VP, _VP, _VP, C.c_int]
     L.grim_stream_add.argtypes = [_VP, _VP, _VP, _VP, C.c_size_t]
@@ -111,6 +116,7 @@ def load():
     L.grim_mlp_forward.argtypes = [_VP, _VP, C.c_int64, _VP]
     L.grim_mlp_backward.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
     L.grim_mlp_train.argtypes = [_VP, _VP, _VP, C.c_int64, C.POINTER(grim_train_cfg_t), _VP]
+    L.grim_mlp_normalisation.argtypes = [_VP, _VP, _VP, C.c_int64, C.c_int, _VP, _VP, _VP]
     L.grim_collect_pairs.argtypes = [_VP, _D, C.c_int, C.c_int, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)]
     _lib = L
     return L
@@ -118,6 +124,7 @@ def load():
 
 def exported_symbols():
     return ["grim_create", "grim_destroy", "grim_last_error", "grim_last_global_error", "grim_device_bytes",
+            "grim_workspace_bytes", "grim_bind_workspace", "grim_mlp_normalisation",
             "grim_set_prims", "grim_get_prims", "grim_cfl_dt", "grim_run", "grim_residual", "grim_stage_solve",
             "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_math_probe", "grim_profile", "grim_kernel_times",
             "grim_mlp_set_weights", "grim_mlp_get_weights", "grim_mlp_forward", "grim_mlp_backward",
@@ -172,6 +179,8 @@ def config_from_workload(wl: dict) -> grim_config_t:
     c.floors = 1 if wl.get("floors", False) else 0
     c.rho_floor = wl.get("rho_floor", 1e-5)
     c.u_floor = wl.get("u_floor", 1e-7)
+    c.ls_safeguard = int(wl.get("ls_safeguard", 0))
+    c.external_workspace = 1 if wl.get("workspace", "library") == "caller" else 0
     return c
 
 
@@ -213,10 +222,13 @@ def grim_residual(ctx, Pn, PE, dtp, P, R, rnorm=None):
     _check(ctx, load().grim_residual(ctx, _ptr(Pn), _ptr(PE), dtp, _ptr(P), _ptr(R), _ptr(rnorm)), "grim_residual")
 
 
-def grim_stage_solve(ctx, Pn, PE, dtp, guess, P_out, iters=None, resid=None, flags=None):
+def grim_stage_solve(ctx, Pn, PE, dtp, guess, P_out, iters=None, resid=None, flags=None, backtracks=None,
+                     want_stats=False):
+    st = grim_stats_t()
     rc = load().grim_stage_solve(ctx, _ptr(Pn), _ptr(PE), dtp, _ptr(guess), _ptr(P_out), _ptr(iters),
-                                 _ptr(resid), _ptr(flags))
+                                 _ptr(resid), _ptr(flags), _ptr(backtracks), C.byref(st) if want_stats else None)
     _check(ctx, rc, "grim_stage_solve")
+    return st.as_dict() if want_stats else None
 
 
 def grim_explicit(ctx, PE, divF, srcE, emhd_sp=None):
@@ -289,10 +301,30 @@ def grim_device_bytes(ctx):
     return int(load().grim_device_bytes(ctx))
 
 
+def grim_workspace_bytes(cfg: grim_config_t):
+    n = int(load().grim_workspace_bytes(C.byref(cfg)))
+    if n == 0:
+        _check(None, -1, "grim_workspace_bytes")
+    return n
+
+
+def grim_bind_workspace(ctx, buf, nbytes):
+    _check(ctx, load().grim_bind_workspace(ctx, _ptr(buf), int(nbytes)), "grim_bind_workspace")
+
+
+def grim_mlp_normalisation(ctx, X, T, n, n_used):
+    xm, xs, ys = np.zeros(MLP_IN), np.zeros(MLP_IN), np.zeros(MLP_OUT)
+    _check(ctx, load().grim_mlp_normalisation(ctx, _ptr(X), _ptr(T), int(n), int(n_used), xm.ctypes.data,
+                                              xs.ctypes.data, ys.ctypes.data), "grim_mlp_normalisation")
+    return xm, xs, ys
+
+
 # ---------------------------------------------------------------- convenience
 
 class Context:
-    """One libgrim context for a workload dict; tensors are torch (cuda) float64."""
+    """One libgrim context for a workload dict; tensors are torch (cuda) float64.
+    With wl["workspace"] == "caller" the device memory is a torch uint8 tensor
+    (self.workspace) handed to the library with grim_bind_workspace."""
 
     def __init__(self, wl: dict, stream=None):
         import torch
@@ -307,11 +339,18 @@ class Context:
         self.stream = stream
         handle = None if stream is None else _VP(stream.cuda_stream)
         self.ctx = grim_create(self.cfg, handle)
+        self.workspace = None
+        if self.cfg.external_workspace:
+            nbytes = grim_workspace_bytes(self.cfg)
+            # torch's caching allocator hands out blocks on 512-byte boundaries
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            grim_bind_workspace(self.ctx, self.workspace, nbytes)
 
     def close(self):
         if self.ctx:
             grim_destroy(self.ctx)
             self.ctx = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -362,7 +401,9 @@ class Context:
         grim_residual(self.ctx, Pn, PE, dtp, P, R, rn)
         return R, rn
 
-    def stage_solve(self, Pn, PE, dtp, guess=None):
+    def stage_solve(self, Pn, PE, dtp, guess=None, extra=False):
+        """(P, iters, resid, flags) of one stage; with extra=True also the
+        per-zone rejected line-search trials and the stage's statistics."""
         t = self.torch
         Pn, PE = self._dev(Pn), self._dev(PE)
         g = None if guess is None else self._dev(guess)
@@ -370,7 +411,10 @@ class Context:
         it = t.empty((self.nz,), dtype=t.int32, device="cuda")
         rr = self.empty((self.nz,))
         fl = t.empty((self.nz,), dtype=t.uint8, device="cuda")
-        grim_stage_solve(self.ctx, Pn, PE, dtp, g, out, it, rr, fl)
+        bt = t.empty((self.nz,), dtype=t.int32, device="cuda") if extra else None
+        st = grim_stage_solve(self.ctx, Pn, PE, dtp, g, out, it, rr, fl, bt, want_stats=extra)
+        if extra:
+            return out, it, rr, fl, bt, st
         return out, it, rr, fl
 
     def explicit(self, PE):

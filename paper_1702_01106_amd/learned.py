@@ -2,8 +2,9 @@
 bookkeeping only; every pair, gradient and update is computed by libgrim).
 
 Pairs come from the plain FP64 solver on training seeds; the input and output
-normalisation are the pairs' mean / standard deviation; the weights start
-from a seeded He initialisation; training is Adam on the GPU.
+normalisation are the pairs' mean / standard deviation (computed by libgrim);
+the weights start from a seeded He initialisation; training is Adam on the
+GPU.
 """
 from __future__ import annotations
 
@@ -35,18 +36,12 @@ def collect(wl: dict, seeds, steps: int, stride: int, cap: int):
     return X[:n], T[:n]
 
 
-def normalisation(X, T, n_used: int):
+def normalisation(ctx, X, T, n_used: int):
     """Input mean and 1/std (0 for constant inputs); output std, 0 for an
     output that is constant over the pairs (for example the third velocity
-    of a 2-D run) or unused, which holds that output at exactly zero."""
-    x = X.double()
-    xm = x.mean(dim=0)
-    xs = x.std(dim=0)
-    istd = np.where(xs.cpu().numpy() > 0, 1.0 / np.maximum(xs.cpu().numpy(), 1e-300), 0.0)
-    ys = np.zeros(grim.MLP_OUT)
-    t = T.double()[:, :n_used].std(dim=0).cpu().numpy()
-    ys[:n_used] = np.where(t > 0, t, 0.0)
-    return xm.cpu().numpy(), istd, ys
+    of a 2-D run) or unused, which holds that output at exactly zero.
+    Computed by libgrim (grim_mlp_normalisation)."""
+    return grim.grim_mlp_normalisation(ctx.ctx, X, T, X.shape[0], n_used)
 
 
 def he_init(seed: int, x_mean, x_istd, y_scale):
@@ -76,9 +71,9 @@ def train_guess(wl: dict, seeds=(1, 2, 3, 4), steps: int = None, pairs: int = 1_
     stride = max(1, candidates // pairs)
     X, T = collect(wl, seeds, steps, stride, pairs)
     n_used = N_USED[wl["nvar"]]
-    xm, xs, ys = normalisation(X, T, n_used)
-    w0 = he_init(init_seed, xm, xs, ys)
     ctx = grim.Context(dict(wl, guess="pn"))
+    xm, xs, ys = normalisation(ctx, X, T, n_used)
+    w0 = he_init(init_seed, xm, xs, ys)
     grim.grim_mlp_set_weights(ctx.ctx, w0)
     hist = grim.grim_mlp_train(ctx.ctx, X, T, X.shape[0], epochs, batch, n_used, lr=lr, seed=init_seed)
     w = grim.grim_mlp_get_weights(ctx.ctx)

@@ -48,6 +48,10 @@ WORKLOADS = {
 }
 
 
+# The line search keeps each new lambda within [0.1, 0.5] of the previous one
+# on the torus: with the update as printed, a full Newton step far worse than
+# f(0) gives lambda ~ f(0)/f(1) and Newton crawls in the atmosphere next to
+# the torus (seen on a 28 x 24 x 6 EMHD torus in the CPU tests).
 # Atmosphere floors rho >= 1e-3 r^-3/2, u >= 1e-3 r^-5/2: on r <= 40 they keep
 # u above the finite-difference rule's absolute threshold 5 eps ~ 7.5e-8 for
 # "small" primitives (Sec. 3.1), where the u column of the Jacobian would be
@@ -56,7 +60,7 @@ WORKLOADS = {
 _KERR = dict(
     metric="mks", spin=0.9375, hslope=0.3, gamma=13.0 / 9.0,
     x_start=[float(np.log(1.3)), 0.0, 0.0], x_end=[float(np.log(40.0)), 1.0, float(2.0 * np.pi)],
-    bc=["outflow", "polar", "periodic"], floors=True, rho_floor=1e-3, u_floor=1e-3,
+    bc=["outflow", "polar", "periodic"], floors=True, rho_floor=1e-3, u_floor=1e-3, ls_safeguard=1,
     torus=dict(r_in=6.0, r_max=12.0, kappa=1e-3, beta=100.0, noise=0.04),
 )
 

@@ -92,3 +92,49 @@ def test_flag_constants_match_header():
     hdr = open(os.path.join(ROOT, "include", "grim.h")).read()
     found = dict(re.findall(r"#define GRIM_FLAG_(\w+) (\d+)", hdr))
     assert {k: int(v) for k, v in found.items()} == grim.FLAGS
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (dict(k_max=101), "k_max"),
+    (dict(ls_max=65), "ls_max"),
+    (dict(ls_safeguard=2), "ls_safeguard"),
+])
+def test_solver_limits_rejected(lib, mutate, msg):
+    wl = W.workload("emhd2d_modes_256")
+    wl.update(mutate)
+    cfg = grim.config_from_workload(wl)
+    cfg.ls_safeguard = mutate.get("ls_safeguard", cfg.ls_safeguard)
+    with pytest.raises(grim.GrimError) as e:
+        grim.grim_create(cfg, None)
+    assert msg in str(e.value)
+    assert lib.grim_workspace_bytes(C.byref(cfg)) == 0
+
+
+def test_workspace_bytes(lib):
+    """grim_workspace_bytes (host only, no device): at least the ghosted state
+    arrays (P_n/P_{n+1}, the half step, two hook copies, one face array per
+    direction), the interior rhs/staging/coefficient arrays, per-zone results
+    and the network's per-zone features; at most that plus 256 bytes of
+    alignment per buffer and the fixed-size parts; geometry only for Kerr;
+    0 for an invalid config."""
+    def need(wl):
+        nv = wl["nvar"]
+        n = list(wl["n"]) + [1] * (3 - len(wl["n"]))
+        N = [n[d] + (4 if d < wl["ndim"] else 0) for d in range(3)]
+        cells, nz = N[0] * N[1] * N[2], n[0] * n[1] * n[2]
+        b = 8 * nv * cells * (5 + wl["ndim"]) + 8 * nz * (2 * nv + (13 if nv == 10 else 0))
+        b += nz * (4 + 8 + 1) + 4 * nz * (grim.MLP_IN + grim.MLP_OUT)
+        if wl.get("metric") == "mks":
+            b += 8 * N[0] * N[1] * (4 * 16 + 64)
+        return b
+
+    fixed = 256 * 128 + 32 + 8 * 258 * 48 + 4 * grim.MLP_PARAMS + 2 * (32 * 128 + 128 * 128 + 32 * 128)
+    for wl in (W.workload("emhd2d_modes_256"), W.small("grmhd3d_kerr_128", [20, 16, 8]),
+               W.workload("srmhd1d_alfven_128")):
+        got = lib.grim_workspace_bytes(C.byref(grim.config_from_workload(wl)))
+        lo = need(wl)
+        assert lo <= got <= lo + fixed + 256 * 40, (wl["name"], got, lo)
+        assert got % 256 == 0
+    bad = grim.config_from_workload(dict(W.workload("emhd2d_modes_256"), ndim=4))
+    assert lib.grim_workspace_bytes(C.byref(bad)) == 0
+    assert b"ndim" in lib.grim_last_global_error()

@@ -1,0 +1,132 @@
+"""GPU checks of the C ABI's boundary calls: device memory owned by PyTorch
+(grim_workspace_bytes / grim_bind_workspace), the network normalisation
+computed in the library, and the line-search statistics of grim_stage_solve
+against the oracle on a case that forces backtracking (Sec. 3.2)."""
+import numpy as np
+import pytest
+
+from paper_1702_01106_amd import workloads as W
+from tests.helpers import prim_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _far_guess(Pn):
+    """u three times P_n's and q = 1: on the 2-D EMHD grid below the full
+    Newton step overshoots, and every zone rejects one to four trials before
+    converging (found on the oracle)."""
+    g = Pn.copy()
+    g[1] *= 3.0
+    g[8] = 1.0
+    return g
+
+
+@pytest.mark.parametrize("safeguard", [0, 1])
+def test_forced_backtracks_match_oracle(torch_cuda, oracle_mod, safeguard):
+    """A far guess passed to grim_stage_solve: the per-zone rejected trials
+    and iterations match the oracle's, every zone backtracks, the roots agree
+    and the statistics count the same trials.  A trial whose norm lands
+    within rounding of the acceptance threshold may be decided the other way
+    by either side, so per-zone counts must agree in 99% of the zones (and
+    differ by at most one elsewhere)."""
+    from paper_1702_01106_amd import grim
+
+    wl = dict(W.small("emhd2d_modes_256", [40, 36]), ls_safeguard=safeguard)
+    Pn = W.fourier_modes_2d(wl, seed=3, amp=1e-2)
+    o = oracle_mod.Oracle(wl)
+    dtp = 0.5 * o.cfl_dt(Pn, 0.5)
+    guess = _far_guess(Pn)
+    print(f"forced backtracks, safeguard {safeguard}", flush=True)
+    ref, it, rr, fl, bt = o.stage_ghosted(Pn, o.fill_ghosts(Pn), dtp, guess=guess)
+    assert np.all(fl == 0) and np.all(bt > 0), (np.unique(fl), bt.min())
+    g = grim.Context(wl)
+    gP, git, grr, gfl, gbt, st = g.stage_solve(Pn, Pn, dtp, guess=guess, extra=True)
+    gP, git, gfl, gbt = gP.cpu().numpy(), git.cpu().numpy(), gfl.cpu().numpy(), gbt.cpu().numpy()
+    assert np.all(gfl == 0), np.unique(gfl, return_counts=True)
+    assert np.all(gbt > 0)
+    assert st["n_backtracks"] == int(gbt.sum()) and st["zone_stages"] == Pn[0].size, st
+    print(f"  backtracks oracle {bt.sum()} gpu {gbt.sum()}; same per zone {np.mean(gbt == bt):.4f}, "
+          f"same iters {np.mean(git == it):.4f}", flush=True)
+    assert np.mean(gbt == bt) >= 0.99 and np.abs(gbt - bt).max() <= 1
+    assert np.mean(git == it) >= 0.99 and np.abs(git - it).max() <= 1
+    assert prim_rel_err(gP, ref).max() < 1e-8
+    _, rn = o.residual(Pn, Pn, dtp, gP)
+    assert rn.max() < 2 * wl["tol"]
+
+
+def test_workspace_owned_by_torch(torch_cuda):
+    """A context whose device memory is a torch tensor handed over with
+    grim_bind_workspace steps bit for bit like one that allocates its own;
+    calls before binding, a second binding, and a misaligned or short buffer
+    are rejected."""
+    from paper_1702_01106_amd import grim
+
+    t = torch_cuda
+    wl = W.small("emhd2d_modes_256", [48, 40])
+    P0 = W.fourier_modes_2d(wl, seed=5, amp=1e-2)
+    own = grim.Context(wl)
+    ext = grim.Context(dict(wl, workspace="caller"))
+    nbytes = grim.grim_workspace_bytes(ext.cfg)
+    assert ext.workspace is not None and ext.workspace.numel() == nbytes
+    assert ext.device_bytes() == nbytes and own.device_bytes() == nbytes
+    for c in (own, ext):
+        c.set_prims(P0)
+    dt = own.cfl_dt(0.5)
+    assert ext.cfl_dt(0.5) == dt
+    sa = own.run(dt, 3)
+    sb = ext.run(dt, 3)
+    assert np.array_equal(own.get_prims(), ext.get_prims()) and sa == sb
+    # an unbound context refuses work; binding checks its buffer
+    cfg = grim.config_from_workload(dict(wl, workspace="caller"))
+    ctx = grim.grim_create(cfg, None)
+    try:
+        with pytest.raises(grim.GrimError, match="no workspace"):
+            grim.grim_set_prims(ctx, np.ascontiguousarray(P0), False)
+        buf = t.empty(nbytes + 512, dtype=t.uint8, device="cuda")
+        with pytest.raises(grim.GrimError, match="aligned"):
+            grim.grim_bind_workspace(ctx, buf[8:], nbytes)
+        with pytest.raises(grim.GrimError, match="too small"):
+            grim.grim_bind_workspace(ctx, buf, nbytes - 256)
+        grim.grim_bind_workspace(ctx, buf, nbytes)
+        with pytest.raises(grim.GrimError, match="already bound"):
+            grim.grim_bind_workspace(ctx, buf, nbytes)
+        grim.grim_set_prims(ctx, np.ascontiguousarray(P0), False)
+    finally:
+        grim.grim_destroy(ctx)
+    with pytest.raises(grim.GrimError, match="own workspace"):
+        grim.grim_bind_workspace(own.ctx, ext.workspace, nbytes)
+
+
+def test_normalisation_matches_numpy(torch_cuda):
+    """grim_mlp_normalisation against numpy's FP64 mean and unbiased standard
+    deviation, with a constant input column (1/std = 0) and an output column
+    beyond n_used (scale 0)."""
+    from paper_1702_01106_amd import grim
+
+    rng = np.random.default_rng(8)
+    n = 50_003
+    X = rng.normal(0.3, 2.0, (n, grim.MLP_IN)).astype(np.float32)
+    X[:, 5] = 0.75
+    T = rng.normal(-1.0, 0.01, (n, grim.MLP_OUT)).astype(np.float32)
+    T[:, 2] = 0.0
+    g = grim.Context(W.small("emhd2d_modes_256", [16, 16]))
+    xm, xs, ys = grim.grim_mlp_normalisation(g.ctx, torch_cuda.from_numpy(X).cuda(),
+                                             torch_cuda.from_numpy(T).cuda(), n, 7)
+    Xd, Td = X.astype(np.float64), T.astype(np.float64)
+    assert np.allclose(xm, Xd.mean(axis=0), rtol=1e-12, atol=1e-14)
+    sd = Xd.std(axis=0, ddof=1)
+    assert xs[5] == 0.0
+    keep = sd > 0
+    assert np.allclose(xs[keep], 1.0 / sd[keep], rtol=1e-10)
+    ty = Td.std(axis=0, ddof=1)
+    assert ys[2] == 0.0 and np.all(ys[7:] == 0.0)
+    used = [c for c in range(7) if c != 2]
+    assert np.allclose(ys[used], ty[used], rtol=1e-10)
