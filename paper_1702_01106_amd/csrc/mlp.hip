@@ -378,14 +378,16 @@ __global__ __launch_bounds__(kNormCols* kNormLanes) void k_norm_partial(const fl
     }
 }
 
-// out[col] = (sum over blocks of part[b][col], in block order) * scale
-__global__ void k_norm_final(const double* __restrict__ part, int nb, double scale, double* __restrict__ out)
+// out[col] = (sum over blocks of part[b][col], in block order) / denom.  A
+// division, not a product with 1/denom: the mean of a constant column is
+// then that constant exactly, and its deviations exactly zero.
+__global__ void k_norm_final(const double* __restrict__ part, int nb, double denom, double* __restrict__ out)
 {
     const int col = threadIdx.x;
     if (col >= kNormCols) return;
     double t = 0.0;
     for (int b = 0; b < nb; ++b) t += part[(long)b * kNormCols + col];
-    out[col] = t * scale;
+    out[col] = t / denom;
 }
 
 }  // namespace
@@ -458,9 +460,9 @@ hipError_t mlp_norm_stats(const float* X, const float* T, long n, double* work, 
     double* mean = work + (long)nblocks * kNormCols;
     double* var = mean + kNormCols;
     hipLaunchKernelGGL(k_norm_partial, dim3(nblocks), dim3(kNormCols * kNormLanes), 0, st, X, T, n, mean, 0, work);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, 1.0 / (double)n, mean);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, (double)n, mean);
     hipLaunchKernelGGL(k_norm_partial, dim3(nblocks), dim3(kNormCols * kNormLanes), 0, st, X, T, n, mean, 1, work);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, 1.0 / (double)(n - 1), var);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, work, nblocks, (double)(n - 1), var);
     return hipGetLastError();
 }
 
