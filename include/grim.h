@@ -118,6 +118,10 @@ typedef struct {
                             1: it allocates none, and the caller hands over
                             grim_workspace_bytes(cfg) bytes of device memory
                             with grim_bind_workspace before any other call  */
+    int stage_block;     /* threads per block of the one-kernel stage of 2-D
+                            Minkowski grids: 0 chooses (512 while every tile
+                            fits the device at once, else 256), 256 or 512
+                            forces that size (for tests of both)             */
 } grim_config_t;
 
 /* Per-call solver statistics (a13).  mean_iters is per zone per stage. */

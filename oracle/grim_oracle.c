@@ -1075,29 +1075,30 @@ int oracle_run(const ocfg_t* c, double* P, double dt, int nsteps, ostats_t* st)
 }
 
 /* The residual of every interior zone at the state P, for a stage with the
- * given P_n, P^E and dtp; also the scaled norm used by the solver. */
-int oracle_residual(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* P, double* R,
-                    double* rnorm)
+ * given P_n, ghost-filled P^E and dtp; also the scaled norm used by the
+ * solver. */
+static int o_residual_core(const ocfg_t* c, const olay_t* Lp, const double* Pn, const double* PEg, double dtp,
+                           const double* P, double* R, double* rnorm)
 {
-    olay_t L = o_layout(c);
+    olay_t L = *Lp;
     const int nv = c->nvar;
     const size_t nz = o_zones(&L);
-    double* PEg = (double*)calloc((size_t)nv * L.cells, sizeof(double));
     double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
     double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
     oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
-    o_to_ghosted(c, &L, PE, PEg);
+    if (!divF || !srcE || !sp) { free(divF); free(srcE); free(sp); return -1; }
     o_explicit_stage(c, &L, PEg, divF, srcE, sp);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int kk = 0; kk < L.n[2]; ++kk)
         for (int jj = 0; jj < L.n[1]; ++jj)
             for (int ii = 0; ii < L.n[0]; ++ii) {
                 size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                size_t m = o_cell(&L, ii + L.g[0], jj + L.g[1], kk + L.g[2]);
                 double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX], p[NVMAX], r[NVMAX];
                 o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
                 for (int v = 0; v < nv; ++v) {
                     pn[v] = Pn[(size_t)v * nz + z];
-                    pe[v] = PE[(size_t)v * nz + z];
+                    pe[v] = PEg[(size_t)v * L.cells + m];
                     dz[v] = divF[(size_t)v * nz + z];
                     sz[v] = srcE[(size_t)v * nz + z];
                     p[v] = P[(size_t)v * nz + z];
@@ -1113,11 +1114,32 @@ int oracle_residual(const ocfg_t* c, const double* Pn, const double* PE, double 
                     rnorm[z] = o_norm(nv - 3, rs, dtp / Z.Un[RHO]);
                 }
             }
-    free(PEg);
     free(divF);
     free(srcE);
     free(sp);
     return 0;
+}
+
+int oracle_residual(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* P, double* R,
+                    double* rnorm)
+{
+    olay_t L = o_layout(c);
+    double* PEg = (double*)calloc((size_t)c->nvar * L.cells, sizeof(double));
+    if (!PEg) return -1;
+    o_to_ghosted(c, &L, PE, PEg);
+    int rc = o_residual_core(c, &L, Pn, PEg, dtp, P, R, rnorm);
+    free(PEg);
+    return rc;
+}
+
+int oracle_residual_ghosted(const ocfg_t* c, const double* Pn, const double* PEg, double dtp, const double* P,
+                            double* R, double* rnorm)
+{
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    olay_t L = o_layout(c);
+    return o_residual_core(c, &L, Pn, PEg, dtp, P, R, rnorm);
 }
 
 /* divF, the explicit geometric source and the EMHD P^E-only source parts
@@ -1297,6 +1319,58 @@ double oracle_vmax2(const ocfg_t* c, const double* P, const double* X)
 
 /* Finite-difference Jacobian of the residual of one interior zone (index z in
  * the interior ordering) at state P, for a stage with P_n, P^E and dtp. */
+/* For every interior zone, the finite-difference Jacobian of the Newton
+ * system (the non-magnetic rows and unknowns, Sec. 3.1 and 8.2) at the state
+ * P, for a stage with P_n, ghost-filled P^E and dtp: J[z][i][j] (m x m,
+ * m = nvar - 3), and U_rho(P_n) of the zone, the scale of the Newton norm.
+ * It bounds how far two states whose residual norms are below the tolerance
+ * can lie apart: P_a - P_b = J^-1 (R_a - R_b) to first order. */
+int oracle_system_jacobians_ghosted(const ocfg_t* c, const double* Pn, const double* PEg, double dtp,
+                                    const double* P, double* J, double* urho)
+{
+#ifdef _OPENMP
+    if (c->nthreads > 0) omp_set_num_threads(c->nthreads);
+#endif
+    olay_t L = o_layout(c);
+    const int nv = c->nvar, m = nv - 3;
+    const size_t nz = o_zones(&L);
+    double* divF = (double*)calloc((size_t)nv * nz, sizeof(double));
+    double* srcE = (double*)calloc((size_t)nv * nz, sizeof(double));
+    oemhd_sp_t* sp = (oemhd_sp_t*)calloc(nz, sizeof(oemhd_sp_t));
+    if (!divF || !srcE || !sp) { free(divF); free(srcE); free(sp); return -1; }
+    o_explicit_stage(c, &L, PEg, divF, srcE, sp);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int kk = 0; kk < L.n[2]; ++kk)
+        for (int jj = 0; jj < L.n[1]; ++jj)
+            for (int ii = 0; ii < L.n[0]; ++ii) {
+                size_t z = ((size_t)kk * L.n[1] + jj) * L.n[0] + ii;
+                size_t cm = o_cell(&L, ii + L.g[0], jj + L.g[1], kk + L.g[2]);
+                double X[4], pn[NVMAX], pe[NVMAX], dz[NVMAX], sz[NVMAX];
+                o_zone_X(c, &L, ii + L.g[0], jj + L.g[1], kk + L.g[2], X);
+                for (int v = 0; v < nv; ++v) {
+                    pn[v] = Pn[(size_t)v * nz + z];
+                    pe[v] = PEg[(size_t)v * L.cells + cm];
+                    dz[v] = divF[(size_t)v * nz + z];
+                    sz[v] = srcE[(size_t)v * nz + z];
+                }
+                ozone_t Z;
+                o_zone_setup(c, X, pn, pe, dz, sz, &sp[z], dtp, &Z);
+                oreduced_t Q;
+                Q.z = &Z;
+                Q.m = m;
+                for (int v = 0; v < NVMAX; ++v) Q.P[v] = v < nv ? P[(size_t)v * nz + z] : 0.0;
+                double x[7], R[7];
+                for (int i = 0; i < m; ++i) x[i] = Q.P[o_unknown[i]];
+                o_reduced_residual(&Q, x, R);
+                oracle_fd_jacobian(m, o_reduced_residual, &Q, x, R, c->eps, J + z * (size_t)m * m);
+                urho[z] = Z.Un[RHO];
+            }
+    free(divF);
+    free(srcE);
+    free(sp);
+    return 0;
+}
+
 int oracle_zone_jacobian(const ocfg_t* c, const double* Pn, const double* PE, double dtp, const double* P,
                          long z, double* J, double* Rz)
 {

@@ -75,6 +75,9 @@ int    oracle_stage_ghosted(const ocfg_t* c, const double* Pn, const double* PEg
                             int32_t* backtracks);
 int    oracle_step(const ocfg_t* c, double* P, double dt, ostats_t* st);
 int    oracle_run(const ocfg_t* c, double* P, double dt, int nsteps, ostats_t* st);
+/* As oracle_residual, with P^E given on the ghosted grid (ghosts as given). */
+int    oracle_residual_ghosted(const ocfg_t* c, const double* Pn, const double* PEg, double dtp,
+                               const double* P, double* R, double* rnorm);
 int    oracle_residual(const ocfg_t* c, const double* Pn, const double* PE,
                        double dtp, const double* P, double* R, double* rnorm);
 int    oracle_explicit(const ocfg_t* c, const double* PE, double* divF,
@@ -101,6 +104,10 @@ void   oracle_fd_jacobian(int n, oresid_fn fn, void* ctx, const double* x,
 int    oracle_zone_jacobian(const ocfg_t* c, const double* Pn, const double* PE,
                             double dtp, const double* P, long z, double* J,
                             double* Rz);
+/* Per zone, the FD Jacobian of the Newton system at P (J [nz][m][m],
+ * m = nvar - 3) and U_rho(P_n), for a stage with ghost-filled P^E. */
+int    oracle_system_jacobians_ghosted(const ocfg_t* c, const double* Pn, const double* PEg, double dtp,
+                                       const double* P, double* J, double* urho);
 /* Interior P [nvar][n3][n2][n1] -> ghosted Pg [nvar][N3][N2][N1] with the
  * ghosts filled by the boundary conditions of c. */
 int    oracle_fill_ghosts(const ocfg_t* c, const double* Pint, double* Pg);

@@ -127,6 +127,8 @@ class Oracle:
             L.oracle_step.argtypes = [P, _D, C.c_double, C.POINTER(OStats)]
             L.oracle_run.argtypes = [P, _D, C.c_double, C.c_int, C.POINTER(OStats)]
             L.oracle_residual.argtypes = [P, _D, _D, C.c_double, _D, _D, _D]
+            L.oracle_residual_ghosted.argtypes = [P, _D, _D, C.c_double, _D, _D, _D]
+            L.oracle_system_jacobians_ghosted.argtypes = [P, _D, _D, C.c_double, _D, _D, _D]
             L.oracle_explicit.argtypes = [P, _D, _D, _D, _D]
             L.oracle_cfl_dt.argtypes = [P, _D, C.c_double]
             L.oracle_cfl_dt.restype = C.c_double
@@ -211,6 +213,31 @@ class Oracle:
         rn = np.empty(self.nz)
         self.L.oracle_residual(C.byref(self.cfg), _dp(Pn), _dp(PE), dtp, _dp(P), _dp(R), _dp(rn))
         return R, rn
+
+    def residual_ghosted(self, Pn, PEg, dtp, P):
+        """As residual, with P^E given on the ghosted grid (ghosts as given)."""
+        Pn, P = self._arr(Pn), self._arr(P)
+        PEg = np.ascontiguousarray(PEg, dtype=np.float64)
+        assert PEg.shape == self.ghosted_shape(), (PEg.shape, self.ghosted_shape())
+        R = np.empty(self.shape)
+        rn = np.empty(self.nz)
+        rc = self.L.oracle_residual_ghosted(C.byref(self.cfg), _dp(Pn), _dp(PEg), dtp, _dp(P), _dp(R), _dp(rn))
+        assert rc == 0
+        return R, rn
+
+    def system_jacobians_ghosted(self, Pn, PEg, dtp, P):
+        """Per zone, the FD Jacobian of the Newton system at P ([nz][m][m])
+        and U_rho(P_n) ([nz]), for a stage with ghost-filled P^E."""
+        Pn, P = self._arr(Pn), self._arr(P)
+        PEg = np.ascontiguousarray(PEg, dtype=np.float64)
+        assert PEg.shape == self.ghosted_shape(), (PEg.shape, self.ghosted_shape())
+        m = self.nvar - 3
+        J = np.empty((self.nz, m, m))
+        ur = np.empty(self.nz)
+        rc = self.L.oracle_system_jacobians_ghosted(C.byref(self.cfg), _dp(Pn), _dp(PEg), dtp, _dp(P), _dp(J),
+                                                    _dp(ur))
+        assert rc == 0
+        return J, ur
 
     def explicit(self, PE):
         PE = self._arr(PE)

@@ -171,6 +171,8 @@ int validate(const grim_config_t* g, std::string& why)
     if (g->ls_safeguard != 0 && g->ls_safeguard != 1) return why = "ls_safeguard must be 0 or 1", 1;
     if (g->external_workspace != 0 && g->external_workspace != 1)
         return why = "external_workspace must be 0 or 1", 1;
+    if (g->stage_block != 0 && g->stage_block != 256 && g->stage_block != 512)
+        return why = "stage_block must be 0, 256 or 512", 1;
     if (g->jac_precision != GRIM_JAC_F64 && g->jac_precision != GRIM_JAC_F32) return why = "bad jac_precision", 1;
     if (g->guess != GRIM_GUESS_PN && g->guess != GRIM_GUESS_MLP) return why = "bad guess", 1;
 
@@ -195,6 +197,26 @@ Layout layout_of(const grim_config_t* cfg)
     L.cells = (long)L.N[0] * L.N[1] * L.N[2];
     L.nz = (long)n[0] * n[1] * n[2];
     return L;
+}
+
+// Physical constants of a configuration, with the EMHD rescaling factors
+// sqrt(tau_R / chi), sqrt(tau_R / nu) and the squared diffusion speeds.
+Phys phys_of(const grim_config_t* cfg)
+{
+    Phys ph{};
+    ph.gam = cfg->gamma;
+    ph.gm1 = cfg->gamma - 1.0;
+    ph.tau = cfg->tau_R;
+    ph.chi = cfg->chi;
+    ph.nu = cfg->nu;
+    ph.theta = cfg->plm_theta;
+    if (cfg->model == GRIM_EMHD) {
+        ph.kq = std::sqrt(cfg->tau_R / cfg->chi);
+        ph.kd = std::sqrt(cfg->tau_R / cfg->nu);
+        ph.vq2 = (cfg->gamma - 1.0) * cfg->chi / cfg->tau_R;
+        ph.vd2 = 4.0 * cfg->nu / (3.0 * cfg->tau_R);
+    }
+    return ph;
 }
 
 constexpr int kNormBlocks = 256;  // partial sums of the normalisation kernel
@@ -304,6 +326,7 @@ NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
 {
     NewtonArgs a{};
     a.cus = c->cus;
+    a.block = c->cfg.stage_block;
     a.s = s;
     a.tol = c->cfg.tol;
     a.eps = c->cfg.eps_fd;
@@ -529,19 +552,7 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
     }
     c->nvar = cfg->model;
     c->L = layout_of(cfg);
-    Phys& ph = c->ph;
-    ph.gam = cfg->gamma;
-    ph.gm1 = cfg->gamma - 1.0;
-    ph.tau = cfg->tau_R;
-    ph.chi = cfg->chi;
-    ph.nu = cfg->nu;
-    ph.theta = cfg->plm_theta;
-    if (cfg->model == GRIM_EMHD) {
-        ph.kq = std::sqrt(cfg->tau_R / cfg->chi);
-        ph.kd = std::sqrt(cfg->tau_R / cfg->nu);
-        ph.vq2 = (cfg->gamma - 1.0) * cfg->chi / cfg->tau_R;
-        ph.vd2 = 4.0 * cfg->nu / (3.0 * cfg->tau_R);
-    }
+    c->ph = phys_of(cfg);
     if (!cfg->external_workspace) {
         // the whole workspace in one allocation
         const size_t bytes = carve(cfg, nullptr, nullptr);
@@ -951,3 +962,12 @@ int grim_stream_add(grim_ctx_t* c, const double* a, const double* b, double* cc,
 }
 
 }  // extern "C"
+
+namespace grim {
+
+int check_config(const grim_config_t* cfg, std::string& why) { return validate(cfg, why); }
+Layout grid_layout(const grim_config_t* cfg) { return layout_of(cfg); }
+Phys physics(const grim_config_t* cfg) { return phys_of(cfg); }
+void set_global_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace grim

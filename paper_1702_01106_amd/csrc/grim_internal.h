@@ -6,7 +6,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
+#include "grim.h"
 #include "grim_device.h"
 
 namespace grim {
@@ -186,8 +188,18 @@ struct NewtonArgs {
     // compute units of the device (0 if unknown): a 2-D tiled stage whose
     // tiles all fit at once runs 512-thread blocks (see k_stage)
     int cus;
+    // 0: block size of the 2-D tiled stage chosen from cus; 256 or 512: forced
+    int block;
 };
 constexpr uint8_t kFlagRetry = 32;
+
+// Host helpers of the C ABI (abi.hip): configuration check (non-zero and a
+// reason if invalid), grid layout, physical constants, and the message that
+// grim_last_global_error returns on this thread.
+int check_config(const grim_config_t* cfg, std::string& why);
+Layout grid_layout(const grim_config_t* cfg);
+Phys physics(const grim_config_t* cfg);
+void set_global_error(const std::string& msg);
 
 // launchers (return hipSuccess or the launch error)
 hipError_t launch_fill_ghosts(const Layout& L, int nvar, const int bc[3], double* P, hipStream_t st);

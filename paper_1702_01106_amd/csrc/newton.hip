@@ -853,7 +853,7 @@ hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
     // 512-thread blocks (face phase at two waves per SIMD) while every tile
     // fits the device at once; past that, 256-thread blocks two to a CU
     constexpr int kWide = ND == 2 ? 2 * T::kThreads : T::kThreads;
-    const bool wide = ND == 2 && a.cus > 0 && tiles <= a.cus;
+    const bool wide = ND == 2 && (a.block == 512 || (a.block == 0 && a.cus > 0 && tiles <= a.cus));
     const dim3 grid((unsigned)tiles);
     if (jac_f32) {
         if (wide) hipLaunchKernelGGL((k_stage<NV, ND, float, kWide>), grid, dim3(kWide), 0, st, b);

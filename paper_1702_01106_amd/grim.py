@@ -38,7 +38,7 @@ class grim_config_t(C.Structure):
         ("k_max", C.c_int), ("ls_max", C.c_int),
         ("jac_precision", C.c_int), ("guess", C.c_int),
         ("floors", C.c_int), ("rho_floor", C.c_double), ("u_floor", C.c_double),
-        ("ls_safeguard", C.c_int), ("external_workspace", C.c_int),
+        ("ls_safeguard", C.c_int), ("external_workspace", C.c_int), ("stage_block", C.c_int),
     ]
 
 
@@ -181,6 +181,7 @@ def config_from_workload(wl: dict) -> grim_config_t:
     c.u_floor = wl.get("u_floor", 1e-7)
     c.ls_safeguard = int(wl.get("ls_safeguard", 0))
     c.external_workspace = 1 if wl.get("workspace", "library") == "caller" else 0
+    c.stage_block = int(wl.get("stage_block", 0))
     return c
 
 

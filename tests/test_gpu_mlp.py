@@ -99,6 +99,8 @@ def test_learned_guess_in_the_solver(torch_cuda):
     Newton kernels, and the two build the face fluxes in different code,
     where the compiler may form different multiply-adds; Newton's stopping
     test turns rounding differences into differences below the tolerance.)"""
+    import bench
+    import oracle as O
     from paper_1702_01106_amd import grim, learned
 
     wl = W.small("emhd2d_modes_256", [128, 128])
@@ -113,9 +115,16 @@ def test_learned_guess_in_the_solver(torch_cuda):
     net = grim.Context(dict(wl, guess="mlp"))
     grim.grim_mlp_set_weights(net.ctx, w)
     net.set_prims(P0)
-    st1 = net.run(dt, 10)
+    st1 = net.run(dt, 9)
+    P9 = net.get_prims()
+    st1b = net.run(dt, 1)
     got = net.get_prims()
-    assert st1["n_fail"] == 0 and st1["max_resid"] < wl["tol"]
+    assert st1["n_fail"] == 0 and st1b["n_fail"] == 0 and max(st1["max_resid"], st1b["max_resid"]) < wl["tol"]
+    assert st1b["n_fallback"] < st1b["zone_stages"]  # the learned guess is taken
+    # the learned form's tenth step against the oracle's step from its ninth
+    _, _, rep = bench.oracle_step_checked(O, wl, P9, dt, 0, Pgpu=got)
+    print("learned form vs oracle:", rep)
+    assert rep["within"], rep
     assert prim_rel_err(got, ref).max() < 1e-6
     it0, it1 = sum(st0["mean_iters"]), sum(st1["mean_iters"])
     print("mean iters plain", st0["mean_iters"], "learned", st1["mean_iters"], "fallback", st1["n_fallback"])

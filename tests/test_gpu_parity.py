@@ -253,6 +253,56 @@ def test_stage_solve(torch_cuda, oracle_mod, name, jac):
         assert np.abs(git.astype(int) - it).max() <= 1
 
 
+@pytest.mark.parametrize("block", [256, 512])
+@pytest.mark.parametrize("jac", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["emhd2d_ragged", "ideal2d"])
+def test_stage_solve_block_sizes(torch_cuda, oracle_mod, name, jac, block):
+    """Both block sizes of the 2-D one-kernel stage (256 threads, two tiles
+    to a CU, used past 256 tiles; 512 threads, the faces at two waves per
+    SIMD, used while every tile fits the device), forced through the config,
+    against the oracle: every primitive within 1e-6 of max(|P_v|, family RMS)
+    or what the tolerance leaves open (bench.compare_stage), no failed zone."""
+    import bench
+
+    wl, _ = CASES[name]()
+    wl = dict(wl, jac=jac, stage_block=block)
+    Pn = _state(name, wl)
+    o = oracle_mod.Oracle(wl)
+    dtp = 0.5 * o.cfl_dt(Pn, 0.5)
+    PE = _perturbed(Pn, 4, 1e-4, 1e-3)
+    _say(f"stage solve {name} jac={jac} block={block}")
+    ref, it, rr, fl = o.stage(Pn, PE, dtp)
+    g = _ctx(wl)
+    gP, git, grr, gfl = (x.cpu().numpy() for x in g.stage_solve(Pn, PE, dtp))
+    assert np.all((gfl & ~np.uint8(32)) == 0), np.unique(gfl)
+    rep = bench.compare_stage(o, wl, Pn, o.fill_ghosts(PE), dtp, gP, ref, rr)
+    assert rep["within"], rep
+    if jac == "f64":
+        assert max(rep["rel"].values()) < 1e-8, rep["rel"]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("jac", ["f64", "f32"])
+def test_emhd2d_512_stage_solve(torch_cuda, oracle_mod, jac):
+    """One stage of the 512^2 EMHD workload (1024 tiles, so 256-thread
+    blocks two to a CU) from its initial state, FP64 and FP32 Jacobian,
+    against the oracle on every zone."""
+    import bench
+
+    wl = dict(W.workload("emhd2d_modes_512"), jac=jac)
+    P0 = W.initial_state(wl, seed=0)
+    o = oracle_mod.Oracle(wl)
+    dtp = 0.5 * o.cfl_dt(P0, wl["cfl"])
+    _say(f"512^2 stage solve jac={jac}")
+    ref, it, rr, fl = o.stage(P0, P0, dtp)
+    g = _ctx(wl)
+    gP, git, grr, gfl = (x.cpu().numpy() for x in g.stage_solve(P0, P0, dtp))
+    assert np.all((gfl & ~np.uint8(32)) == 0), np.unique(gfl)
+    rep = bench.compare_stage(o, wl, P0, o.fill_ghosts(P0), dtp, gP, ref, rr)
+    _say(f"  rel {rep['rel']}\n  over allowed {rep['worst_over_allowed']}")
+    assert rep["within"], rep
+
+
 @pytest.mark.parametrize("name", ["srmhd1d", "srmhd1d_300", "emhd2d_ragged", "ideal3d", "kerr_ideal", "kerr_emhd"])
 def test_steps(torch_cuda, oracle_mod, name):
     wl, _ = CASES[name]()
@@ -476,13 +526,24 @@ def test_emhd2d_full_size_sampled(torch_cuda, oracle_mod):
     assert np.abs(o.divb(P50) - o.divb(P0)).max() < 1e-11
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["grmhd3d_kerr_128", "emhd3d_kerr_192"])
 def test_kerr_full_size(torch_cuda, oracle_mod, name):
-    """The Kerr torus workloads at their full sizes: one stage solve on the
-    initial state compared zone by zone with the oracle (FP64 and FP32
-    Jacobian), then the workload's 20 steps on the GPU (graph replay) checked
-    for convergence, finiteness and flux-CT div B."""
+    """The Kerr torus workloads at their full sizes, in the benchmark's
+    launch configuration (graph replay).  One stage solve on the initial
+    state is compared zone by zone with the oracle on the whole grid (FP64
+    and FP32 Jacobian); then the workload's 20 steps run, and at steps 1, 10
+    and 20 the oracle advances the GPU's state on a 32^3 subdomain in the
+    torus body (with a 2 Ng halo).  Each comparison (bench.compare_stage)
+    asks every primitive to be within 1e-6 of max(|P_v|, family RMS), or
+    within twice what the Newton tolerance leaves open where that is larger
+    (||row v of J^-1|| times the two residual norms: it exceeds 1e-6 of the
+    tiny scale of q and DP early in the run), and the oracle's residual at
+    the GPU's answer to be below 2 tol.  The GPU's failure flags in the box
+    equal the oracle's, no zone fails in the whole run, and the flux-CT
+    corner div B is preserved."""
+    import bench
+
     wl = W.workload(name)
     P0 = W.initial_state(wl, seed=0)
     o = oracle_mod.Oracle(wl)
@@ -490,23 +551,42 @@ def test_kerr_full_size(torch_cuda, oracle_mod, name):
     g.set_prims(P0)
     dt = g.cfl_dt(wl["cfl"])
     assert abs(dt - o.cfl_dt(P0, wl["cfl"])) <= 1e-12 * dt
-    _say(f"{name}: oracle stage on the full grid (twice, for its spread)")
+    _say(f"{name}: oracle stage on the full grid")
     ref, it, rr, fl = o.stage(P0, P0, 0.5 * dt)
     assert np.all(fl == 0), np.unique(fl, return_counts=True)
-    spread, _ = _oracle_spread(lambda Q: o.stage(Q, P0, 0.5 * dt)[:2], P0, base=(ref, it))
-    _say(f"  oracle spread {np.array2string(spread, precision=1)}")
+    PEg = o.fill_ghosts(P0)
     for jac in ("f64", "f32"):
         gj = _ctx(dict(wl, jac=jac))
         gP, git, grr, gfl = gj.stage_solve(P0, P0, 0.5 * dt)
         gP, gfl = gP.cpu().numpy(), gfl.cpu().numpy()
+        gj.close()
         assert np.all(gfl == 0), (jac, np.unique(gfl, return_counts=True))
         assert grr.max().item() < wl["tol"]
-        _within_spread(prim_rel_err(gP, ref), spread, 1e-8 if jac == "f64" else 1e-6)
-        gj.close()
-    _say(f"{name}: {wl['steps']} GPU steps")
-    st = g.run(dt, wl["steps"], use_graph=True)
+        rep = bench.compare_stage(o, wl, P0, PEg, 0.5 * dt, gP, ref, rr)
+        _say(f"  {jac}: rel {rep['rel']}\n  over allowed {rep['worst_over_allowed']}")
+        assert rep["within"], rep
+    box = bench.kerr_box(wl)
+    done, nfail = 0, 0
+    for s in (1, 10, 20):
+        if s - 1 > done:
+            nfail += g.run(dt, s - 1 - done, use_graph=True)["n_fail"]
+        Pin = g.get_prims()
+        nfail += g.run(dt, 1, use_graph=True)["n_fail"]
+        done = s
+        Pout = g.get_prims()
+        gfl, git = g.zone_results()
+        shape = (1,) + P0.shape[1:]
+        gfl = bench.cut(gfl.reshape(shape), box, halo=False).ravel()
+        _say(f"{name}: oracle step on the 32^3 box at step {s}")
+        got = bench.cut(Pout, box, halo=False)
+        _, info, rep = bench.oracle_step_checked(oracle_mod, wl, bench.cut(Pin, box, halo=True), dt, 0, box=box,
+                                                 Pgpu=got)
+        _say(f"  rel {rep['rel']}\n  over allowed {rep['worst_over_allowed']}\n  oracle {info}")
+        assert rep["within"], rep
+        assert info["fail_stage1"] == 0 and info["fail_stage2"] == 0
+        assert np.all((gfl & 21) == 0), np.unique(gfl, return_counts=True)
+    assert nfail == 0, nfail
     P1 = g.get_prims()
     assert np.isfinite(P1).all()
-    assert st["n_fail"] <= 1e-4 * st["zone_stages"], st
     d0, d1 = o.divb(P0), o.divb(P1)
     assert np.abs(d1 - d0).max() <= 1e-9 * max(np.abs(d0).max(), 1.0) + 1e-6
