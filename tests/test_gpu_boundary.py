@@ -6,7 +6,6 @@ import numpy as np
 import pytest
 
 from paper_1702_01106_amd import workloads as W
-from tests.helpers import prim_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +41,12 @@ def test_forced_backtracks_match_oracle(torch_cuda, oracle_mod, safeguard):
     norms spread over 1e-11..1e-9 around the tolerance, so whether a zone
     stops at eight or nine is not fixed by the method (the oracle's own
     counts change in ~5% of the zones when its input changes by 1e-14
-    relative); each zone may differ by one, and the mean by 2%."""
+    relative); each zone may differ by one, and the mean by 2%.  The roots
+    are compared like every stage solve: each primitive within 1e-6 of
+    max(|P_v|, family RMS) or twice what the tolerance leaves open (the
+    oracle's J^-1 rows times both final residual norms), whichever is
+    larger, and the oracle's residual at the GPU's root below 2 tol."""
+    import bench
     from paper_1702_01106_amd import grim
 
     wl = dict(W.small("emhd2d_modes_256", [40, 36]), ls_safeguard=safeguard)
@@ -63,9 +67,9 @@ def test_forced_backtracks_match_oracle(torch_cuda, oracle_mod, safeguard):
           f"same iters {np.mean(git == it):.4f}", flush=True)
     assert np.mean(gbt == bt) >= 0.99 and np.abs(gbt - bt).max() <= 1
     assert np.abs(git - it).max() <= 1 and abs(git.mean() - it.mean()) <= 0.02 * it.mean()
-    assert prim_rel_err(gP, ref).max() < 1e-8
-    _, rn = o.residual(Pn, Pn, dtp, gP)
-    assert rn.max() < 2 * wl["tol"]
+    rep = bench.compare_stage(o, wl, Pn, o.fill_ghosts(Pn), dtp, gP, ref, rr)
+    print(f"  rel {rep['rel']}\n  over allowed {rep['worst_over_allowed']}", flush=True)
+    assert rep["within"], rep
 
 
 def test_workspace_owned_by_torch(torch_cuda):
