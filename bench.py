@@ -130,6 +130,11 @@ def stream_probe(grim, wl, n: int = 1 << 26, reps: int = 20) -> dict:
     return {"gbs": 3 * 8 * n * reps / t / 1e9, "bytes_per_launch": 3 * 8 * n, "exact": ok}
 
 
+def log(msg: str) -> None:
+    """Progress of the benchmark's phases on stderr (the JSON line is stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 # ------------------------------------------------------------------ GPU runs
 
 def timed_run(grim, wl, P0, steps, warmup, weights=None):
@@ -259,6 +264,8 @@ def run_forms(grim, W, wl, P0, args, names):
             torch.cuda.synchronize()
             res["training"] = {"pairs": info["pairs"], "epochs": args.epochs, "seconds": time.perf_counter() - t0,
                                "loss_first_last": [info["loss"][0], info["loss"][-1]], "seeds": [1, 2, 3, 4]}
+            log(f"{wl['name']}: trained the guess network on {info['pairs']} pairs in "
+                f"{res['training']['seconds']:.1f} s")
         fwl = dict(wl, jac=jac, guess="mlp" if learned_guess else "pn")
         w = weights if learned_guess else None
         dt, t, st, st_p, times, _ = timed_run(grim, fwl, P0, args.steps, args.warmup, weights=w)
@@ -268,6 +275,8 @@ def run_forms(grim, W, wl, P0, args, names):
         line["stats_eager_pass"] = st_p
         line["dt"] = dt
         res[name] = line
+        log(f"{wl['name']} {name}: {line['value']:.4g} zone-updates/s, {line['ms_per_step']:.3f} ms/step, "
+            f"iters {line['mean_newton_iters']}")
         checks[name] = check_states(grim, fwl, P0, dt, args.steps, weights=w, box=box)
     return res, checks
 
@@ -447,6 +456,7 @@ def cpu_leg(W, wl, forms, checks, variant_checks):
         errs = {}
         for s, Pin, Pout in states:
             _, info, rep = oracle_step_checked(O, wl, Pin, forms[name]["dt"], threads, box=box, Pgpu=Pout)
+            log(f"oracle check {name} step {s}: within {rep['within']}")
             if name == "f64":
                 t_all += info["oracle_seconds"]
                 zone_updates += Pout[0].size
