@@ -53,6 +53,21 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// Column order of the zones of a 3-D grid (the Kerr metric tables depend on
+// (i, j) only): logical wave w covers 64 consecutive i of row j in plane k,
+// with k fastest, so successive waves read the same table points.  Total
+// waves: ceil(n1 / 64) * n2 * n3.  Returns false for lanes past the row's end
+// and for waves past the last.
+__device__ __forceinline__ bool column_zone(const Layout& L, unsigned w, unsigned lane, long& z)
+{
+    const unsigned nic = ((unsigned)L.n[0] + 63u) / 64u, nk = (unsigned)L.n[2];
+    const unsigned k = w % nk, r = w / nk, ic = r % nic, j = r / nic;
+    const unsigned i = ic * 64u + lane;
+    z = ((long)k * L.n[1] + j) * L.n[0] + i;
+    return i < (unsigned)L.n[0] && j < (unsigned)L.n[1];
+}
+inline long column_waves(const Layout& L) { return (long)((L.n[0] + 63) / 64) * L.n[1] * L.n[2]; }
+
 // Block order of the Kerr flux kernel, which reads 2-D (i, j) face metric
 // tables shared by every plane k: block b covers the points
 // [chunk * width, chunk * width + width) of plane k, with k = b % planes and

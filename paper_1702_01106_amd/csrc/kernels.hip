@@ -126,10 +126,16 @@ __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
 template <int NV, class G, int ND>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_rhs(StageArgs a)
 {
-    // plain block order: the plane-interleaved order that speeds up the Kerr
-    // flux kernel made this one 16% slower on the 128x128x64 torus (5% faster
-    // on the 192x192x96 one), and the XCD renumbering 5-20% slower
-    const long z = (long)blockIdx.x * kBlock + threadIdx.x;
+    // Kerr 3-D: column order (column_zone), the block's four waves in four
+    // successive planes of one row segment, so they share its metric and
+    // connection table points (5% faster on both tori than the plain order;
+    // adding the XCD renumbering made it slower again)
+    long z;
+    if constexpr (!G::kFlat && ND == 3) {
+        if (!column_zone(a.L, blockIdx.x * (kBlock / 64) + threadIdx.x / 64, threadIdx.x % 64, z)) return;
+    } else {
+        z = (long)blockIdx.x * kBlock + threadIdx.x;
+    }
     if (z >= a.L.nz) return;
     double rhs[NV], co[kEmhdCoef];
     G g;
@@ -309,7 +315,8 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
 template <int NV, class G>
 hipError_t rhs_t(const StageArgs& a, hipStream_t st)
 {
-    const dim3 grid(nblocks(a.L.nz)), blk(kBlock);
+    const bool col = !G::kFlat && a.L.ndim == 3;
+    const dim3 grid(col ? nblocks(column_waves(a.L), kBlock / 64) : nblocks(a.L.nz)), blk(kBlock);
     if (a.L.ndim == 1) hipLaunchKernelGGL((k_rhs<NV, G, 1>), grid, blk, 0, st, a);
     else if (a.L.ndim == 2) hipLaunchKernelGGL((k_rhs<NV, G, 2>), grid, blk, 0, st, a);
     else hipLaunchKernelGGL((k_rhs<NV, G, 3>), grid, blk, 0, st, a);
