@@ -270,6 +270,20 @@ int grim_mlp_forward(grim_ctx_t* ctx, const float* X, int64_t n, float* Y);
  * pointers.  Synchronises. */
 int grim_mlp_backward(grim_ctx_t* ctx, const float* X, const float* dY, int64_t n, float* dW);
 
+/* The gradient of grim_mlp_backward for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc): same arguments and result, but it calls
+ * no allocating routine.  Its work buffers live in a device array of the
+ * library (about 6.9 MB on each GPU it runs on, held until the process
+ * ends) that holds at most 2048 rows: n must be in [1, 2048]
+ * (GRIM_E_INVALID_ARG beyond).  Asynchronous: enqueued on the context's
+ * stream, with no synchronisation, so it may be captured; dW is ready when
+ * that stream has reached it.  Every call on one GPU shares that array,
+ * whatever the context: calls that overlap on one GPU (two streams, or two
+ * host threads) race, and the caller must order them.  Errors as for
+ * grim_mlp_backward. */
+int grim_mlp_backward_noalloc(grim_ctx_t* ctx, const float* X, const float* dY, int64_t n, float* dW);
+
 /* Adam on the mean squared error over the first n_used outputs, on n pairs
  * X [n][32], T [n][16] (device); shuffled each epoch; FP32 master weights,
  * normalisation entries fixed.  loss_hist (host, cfg->epochs doubles, may be

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <type_traits>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -68,6 +69,7 @@ struct grim_ctx {
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     double graph_dt = 0.0;
     int cus = 0;  // compute units of the device (0 if the query failed)
+    float* scratch = nullptr;  // this device's copy of the no-allocation scratch array
     bool timing = false;
     struct Mark {
         int group;
@@ -91,6 +93,46 @@ int fail(grim_ctx* c, int code, const std::string& msg)
 int hip_fail(grim_ctx* c, hipError_t e, const char* what)
 {
     return fail(c, GRIM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---- scratch of the no-allocation gradient call (grim_mlp_backward_noalloc)
+//
+// The ten per-row work buffers of one gradient pass (network input and
+// target, the two hidden layers before and after GELU, the output, its
+// gradient and the two hidden gradients: 848 floats a row) for up to
+// kNoAllocRows rows, then one double for the loss accumulator the kernels
+// take.  A file-scope device array, so the call allocates nothing; each GPU
+// holds its own copy (about 6.9 MB) until the process ends.  Host code never
+// names the array itself (on the host its name is a stand-in, not a device
+// address): grim_create resolves its address on the context's device with
+// hipGetSymbolAddress, once per device, and every launch takes that pointer.
+constexpr int kNoAllocRows = 2048;
+constexpr int kRowFloats = grim::kMlpIn + grim::kMlpOut + 6 * grim::kMlpHidden + 2 * grim::kMlpOut;
+static_assert(kRowFloats == 848, "work buffer widths");
+constexpr size_t kScratchFloats = (size_t)kNoAllocRows * kRowFloats + 64;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch` (resolved on first use on that
+// device); hipSuccess or the error of the lookup.
+hipError_t scratch_address(float** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
 }
 
 // A context whose device memory is in place (create allocated it, or a
@@ -550,6 +592,16 @@ int grim_create(const grim_config_t* cfg, void* hip_stream, grim_ctx_t** out)
             hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             c->cus = 0;
     }
+    {
+        // this device's copy of the no-allocation scratch array
+        const hipError_t e = scratch_address(&c->scratch);
+        if (e != hipSuccess) {
+            g_last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            release(c);
+            delete c;
+            return GRIM_E_HIP;
+        }
+    }
     c->nvar = cfg->model;
     c->L = layout_of(cfg);
     c->ph = phys_of(cfg);
@@ -855,6 +907,36 @@ int grim_mlp_backward(grim_ctx_t* c, const float* X, const float* dY, int64_t n,
                                         off > 0 ? 1 : 0, c->dloss, c->st));
     }
     HIP_TRY(c, hipStreamSynchronize(c->st));
+    return GRIM_OK;
+}
+
+int grim_mlp_backward_noalloc(grim_ctx_t* c, const float* X, const float* dY, int64_t n, float* dW)
+{
+    if (int rc_ = usable(c)) return rc_;
+    if (!X || !dY || !dW || n <= 0) return fail(c, GRIM_E_INVALID_ARG, "bad arguments");
+    if (n > kNoAllocRows)
+        return fail(c, GRIM_E_INVALID_ARG,
+                    "n = " + std::to_string(n) + " rows exceeds the " + std::to_string(kNoAllocRows) +
+                        " rows of the no-allocation scratch");
+    if (!c->mlp_set) return fail(c, GRIM_E_STATE, "no network weights set");
+    if (!c->scratch) return fail(c, GRIM_E_STATE, "no scratch address for this device");
+    grim::MlpWork w{};
+    float* q = c->scratch;
+    float** bufs[] = {&w.xh, &w.tb, &w.z1, &w.h1, &w.z2, &w.h2, &w.o, &w.d_o, &w.dh, &w.dh1};
+    const int widths[] = {grim::kMlpIn, grim::kMlpOut, grim::kMlpHidden, grim::kMlpHidden, grim::kMlpHidden,
+                          grim::kMlpHidden, grim::kMlpOut, grim::kMlpOut, grim::kMlpHidden, grim::kMlpHidden};
+    for (int i = 0; i < 10; ++i) {
+        *bufs[i] = q;
+        q += (size_t)kNoAllocRows * widths[i];
+    }
+    w.cap = kNoAllocRows;
+    double* loss = reinterpret_cast<double*>(q);  // 256-byte aligned: every buffer is a multiple of it
+    // every work buffer is written before it is read, and the layers' weight
+    // and bias gradients are written, not accumulated (acc = 0); only the
+    // normalisation entries of dW, which no kernel writes, are cleared (by
+    // a fill kernel, so the call can be captured in a graph)
+    HIP_TRY(c, grim::mlp_fill(dW + grim::kOffXm, grim::kMlpParams - grim::kOffXm, 0.0f, c->st));
+    HIP_TRY(c, grim::mlp_batch_grad(w, X, nullptr, dY, nullptr, 0, (int)n, 0, 0.0f, c->mlp_p, dW, 0, loss, c->st));
     return GRIM_OK;
 }
 

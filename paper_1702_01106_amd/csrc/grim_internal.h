@@ -240,6 +240,7 @@ hipError_t mlp_infer(const float* X, long n, const float* params, const unsigned
 hipError_t mlp_batch_grad(const MlpWork& w, const float* X, const float* T, const float* dY, const int* idx,
                           long off, int nbatch, int n_used, float inv_count, const float* p, float* grad, int acc,
                           double* loss, hipStream_t st);
+hipError_t mlp_fill(float* p, long n, float v, hipStream_t st);
 hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                     int step, hipStream_t st);
 // Means and unbiased variances of the 32 input and 16 target columns of n

@@ -445,6 +445,19 @@ hipError_t mlp_batch_grad(const MlpWork& w, const float* X, const float* T, cons
     return hipGetLastError();
 }
 
+static __global__ void k_fill(float* __restrict__ p, long n, float v)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t mlp_fill(float* p, long n, float v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nb(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                     int step, hipStream_t st)
 {

@@ -115,6 +115,7 @@ def load():
     L.grim_mlp_get_weights.argtypes = [_VP, _VP, C.c_size_t]
     L.grim_mlp_forward.argtypes = [_VP, _VP, C.c_int64, _VP]
     L.grim_mlp_backward.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
+    L.grim_mlp_backward_noalloc.argtypes = [_VP, _VP, _VP, C.c_int64, _VP]
     L.grim_mlp_train.argtypes = [_VP, _VP, _VP, C.c_int64, C.POINTER(grim_train_cfg_t), _VP]
     L.grim_mlp_normalisation.argtypes = [_VP, _VP, _VP, C.c_int64, C.c_int, _VP, _VP, _VP]
     L.grim_collect_pairs.argtypes = [_VP, _D, C.c_int, C.c_int, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)]
@@ -128,6 +129,7 @@ def exported_symbols():
             "grim_set_prims", "grim_get_prims", "grim_cfl_dt", "grim_run", "grim_residual", "grim_stage_solve",
             "grim_explicit", "grim_get_zone_results", "grim_stream_add", "grim_math_probe", "grim_profile", "grim_kernel_times",
             "grim_mlp_set_weights", "grim_mlp_get_weights", "grim_mlp_forward", "grim_mlp_backward",
+            "grim_mlp_backward_noalloc",
             "grim_mlp_train", "grim_collect_pairs"]
 
 
@@ -280,6 +282,12 @@ def grim_mlp_forward(ctx, X, n, Y):
 
 def grim_mlp_backward(ctx, X, dY, n, dW):
     _check(ctx, load().grim_mlp_backward(ctx, _ptr(X), _ptr(dY), int(n), _ptr(dW)), "grim_mlp_backward")
+
+
+def grim_mlp_backward_noalloc(ctx, X, dY, n, dW):
+    """Asynchronous (enqueued on the context's stream); n <= 2048 rows."""
+    _check(ctx, load().grim_mlp_backward_noalloc(ctx, _ptr(X), _ptr(dY), int(n), _ptr(dW)),
+           "grim_mlp_backward_noalloc")
 
 
 def grim_mlp_train(ctx, X, T, n, epochs, batch, n_used, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
