@@ -257,14 +257,67 @@ static void o_tmunu(const ocfg_t* c, const double* P, const ostate_t* S, double 
         }
 }
 
+/* Sound speed squared of a state, cs^2 = gamma (gamma-1) u / (rho + gamma u)
+ * (Sec. 4.1, below eq. modcs). */
+static double o_cs2(const ocfg_t* c, const double* P)
+{
+    return c->gam * (c->gam - 1.0) * P[UU] / (P[RHO] + c->gam * P[UU]);
+}
+
+/* chi / tau_R and nu / tau_R of a state.  Without the closure both are the
+ * given constants over the given tau_R; with the closure of Sec. 4 (closing
+ * paragraph), chi = phi cs^2 tau_R and nu = psi cs^2 tau_R, so the ratios
+ * are phi cs^2 and psi cs^2 whatever tau_R is. */
+static void o_diff_over_tau(const ocfg_t* c, const double* P, double* chi_t, double* nu_t)
+{
+    if (c->closure) {
+        double cs2 = o_cs2(c, P);
+        *chi_t = c->phi * cs2;
+        *nu_t = c->psi * cs2;
+    } else {
+        *chi_t = c->chi / c->tau_R;
+        *nu_t = c->nu / c->tau_R;
+    }
+}
+
 /* Rescaled dissipative variables, eqs. (q) and (dP):
  * qtilde = q sqrt(tau_R / (chi rho Theta^2)), DPtilde = DP sqrt(tau_R / (nu rho Theta)),
- * with Theta = P/rho. */
+ * with Theta = P/rho, chi and nu those of the state itself. */
 static void o_rescaled(const ocfg_t* c, const double* P, const ostate_t* S, double* qt, double* dpt)
 {
     double theta = S->pg / P[RHO];
-    *qt = P[QQ] * sqrt(c->tau_R / (c->chi * P[RHO] * theta * theta));
-    *dpt = P[DP] * sqrt(c->tau_R / (c->nu * P[RHO] * theta));
+    if (c->closure) {
+        double chi_t, nu_t;
+        o_diff_over_tau(c, P, &chi_t, &nu_t);
+        *qt = P[QQ] * sqrt(1.0 / (chi_t * P[RHO] * theta * theta));
+        *dpt = P[DP] * sqrt(1.0 / (nu_t * P[RHO] * theta));
+    } else {
+        *qt = P[QQ] * sqrt(c->tau_R / (c->chi * P[RHO] * theta * theta));
+        *dpt = P[DP] * sqrt(c->tau_R / (c->nu * P[RHO] * theta));
+    }
+}
+
+/* The relaxation time of a zone's stage, taken at P^E.  Without saturation
+ * it is tau_R.  With it (reading: the paper saturates DeltaP at the firehose
+ * threshold -b^2 and the mirror threshold b^2/2 by reducing tau_R smoothly,
+ * Sec. 8.1 and Sec. 9, and gives no formula): x = -DeltaP/b^2 for DeltaP < 0
+ * and x = 2 DeltaP/b^2 for DeltaP > 0 measure the anisotropy against its
+ * threshold, and tau = tau_R for x <= 1, tau = tau_R / (1 + ((x-1)/w)^2)
+ * beyond (w = sat_width, a C^1 switch), never below 1e-6 tau_R; b^2 is
+ * floored at 1e-30.  With the closure chi and nu scale with tau, so DeltaP_0
+ * shrinks with it and the relaxation toward it speeds up. */
+static double o_tau_eff(const ocfg_t* c, const double* P, const ostate_t* S)
+{
+    if (!c->dp_saturation) return c->tau_R;
+    double b2 = S->bsq > 1e-30 ? S->bsq : 1e-30;
+    double x = P[DP] < 0.0 ? -P[DP] / b2 : 2.0 * P[DP] / b2;
+    double f = 1.0;
+    if (x > 1.0) {
+        double y = (x - 1.0) / c->sat_width;
+        f = 1.0 / (1.0 + y * y);
+        if (f < 1e-6) f = 1e-6;
+    }
+    return c->tau_R * f;
 }
 
 /* dir = 0: conserved vector U; dir = d in 1..3: flux F^d.
@@ -297,7 +350,8 @@ static void o_flux_from_state(const ocfg_t* c, const double* P, const ogeom_t* G
  * v_max^2 = ct^2 + vA^2 - ct^2 vA^2, vA^2 = b^2/(rho + gamma u + b^2),
  * cs^2 = gamma (gamma-1) u/(rho + gamma u),
  * ct^2 = (cs^2 + vq^2 + sqrt(cs^4 + vq^4))/2 + vdP^2,
- * vq^2 = (gamma-1) chi/tau_R, vdP^2 = 4 nu/(3 tau_R).  Ideal MHD: ct = cs. */
+ * vq^2 = (gamma-1) chi/tau_R, vdP^2 = 4 nu/(3 tau_R), chi and nu those of the
+ * state (o_diff_over_tau).  Ideal MHD: ct = cs. */
 static double o_vmax2_state(const ocfg_t* c, const double* P, const ostate_t* S)
 {
     double g = c->gam;
@@ -305,8 +359,14 @@ static double o_vmax2_state(const ocfg_t* c, const double* P, const ostate_t* S)
     double va2 = S->bsq / (P[RHO] + g * P[UU] + S->bsq);
     double ct2 = cs2;
     if (c->nvar == 10) {
-        double vq2 = (g - 1.0) * c->chi / c->tau_R;
-        double vd2 = 4.0 * c->nu / (3.0 * c->tau_R);
+        double vq2, vd2;
+        if (c->closure) {
+            vq2 = (g - 1.0) * c->phi * cs2;
+            vd2 = 4.0 * c->psi * cs2 / 3.0;
+        } else {
+            vq2 = (g - 1.0) * c->chi / c->tau_R;
+            vd2 = 4.0 * c->nu / (3.0 * c->tau_R);
+        }
         ct2 = 0.5 * (cs2 + vq2 + sqrt(cs2 * cs2 + vq2 * vq2)) + vd2;
     }
     return ct2 + va2 - ct2 * va2;
@@ -350,8 +410,85 @@ static size_t o_stride(const olay_t* L, int d)
     return d == 0 ? 1 : (d == 1 ? (size_t)L->N[0] : (size_t)L->N[0] * L->N[1]);
 }
 
-/* LLF flux through the face on the low side of cell (i,j,k) in direction d
- * (Sec. 2.4.1 reconstruction, Sec. 2.4.2 LLF). */
+/* WENO5 (Jiang & Shu's fifth-order weighted essentially non-oscillatory
+ * interpolation, the scheme Sec. 2.3 names): the value at the right face of
+ * the middle cell of the five equally spaced cell values a..e, as the
+ * weighted mean of the three third-order values of the stencils (a,b,c),
+ * (b,c,d), (c,d,e), with ideal weights 1/10, 6/10, 3/10 and the
+ * smoothness indicators of that method; epsilon = 1e-6 (reading: the paper
+ * gives none). */
+static double o_weno5(double a, double b, double cc, double d, double e)
+{
+    double q0 = (2.0 * a - 7.0 * b + 11.0 * cc) / 6.0;
+    double q1 = (-b + 5.0 * cc + 2.0 * d) / 6.0;
+    double q2 = (2.0 * cc + 5.0 * d - e) / 6.0;
+    double s0 = 13.0 / 12.0 * (a - 2.0 * b + cc) * (a - 2.0 * b + cc) + 0.25 * (a - 4.0 * b + 3.0 * cc) * (a - 4.0 * b + 3.0 * cc);
+    double s1 = 13.0 / 12.0 * (b - 2.0 * cc + d) * (b - 2.0 * cc + d) + 0.25 * (b - d) * (b - d);
+    double s2 = 13.0 / 12.0 * (cc - 2.0 * d + e) * (cc - 2.0 * d + e) + 0.25 * (3.0 * cc - 4.0 * d + e) * (3.0 * cc - 4.0 * d + e);
+    const double eps = 1e-6;
+    double w0 = 0.1 / ((eps + s0) * (eps + s0));
+    double w1 = 0.6 / ((eps + s1) * (eps + s1));
+    double w2 = 0.3 / ((eps + s2) * (eps + s2));
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+/* PPM (Colella & Woodward's piecewise parabolic method, the other scheme
+ * Sec. 2.3 names): face values of the middle cell of a..e.  Each face value
+ * starts as the fourth-order interpolant 7/12 (sum of the two neighbours) -
+ * 1/12 (sum of the next two), bounded by its two neighbouring cell values;
+ * then the parabola is made monotone: at a local extremum both face values
+ * become the cell value, and where the parabola would overshoot, the far
+ * face value is moved so that its extremum sits on the near face. */
+static void o_ppm(double a, double b, double cc, double d, double e, double* left, double* right)
+{
+    double l = 7.0 / 12.0 * (b + cc) - 1.0 / 12.0 * (a + d);
+    double r = 7.0 / 12.0 * (cc + d) - 1.0 / 12.0 * (b + e);
+    l = fmin(fmax(l, fmin(b, cc)), fmax(b, cc));
+    r = fmin(fmax(r, fmin(cc, d)), fmax(cc, d));
+    if ((r - cc) * (cc - l) <= 0.0) {
+        l = cc;
+        r = cc;
+    } else {
+        double dd = r - l, m6 = 6.0 * (cc - 0.5 * (l + r));
+        if (dd * m6 > dd * dd) l = 3.0 * cc - 2.0 * r;
+        else if (-dd * dd > dd * m6) r = 3.0 * cc - 2.0 * l;
+    }
+    *left = l;
+    *right = r;
+}
+
+/* Left and right states of one variable at the face between cells i-1 and
+ * i, from the cell values s[0..5] of cells i-3..i+2 (PLM reads s[1..4]):
+ * the left state is cell i-1's value at its right face, the right state
+ * cell i's value at its left face (the mirrored stencil) (Sec. 2.4.1). */
+static void o_recon(const ocfg_t* c, const double* s, double* left, double* right)
+{
+    if (c->recon == 0) {
+        double sl = o_gmm(s[2] - s[1], s[3] - s[2], c->theta_plm);
+        double sr = o_gmm(s[3] - s[2], s[4] - s[3], c->theta_plm);
+        *left = s[2] + 0.5 * sl;
+        *right = s[3] - 0.5 * sr;
+    } else if (c->recon == 1) {
+        *left = o_weno5(s[0], s[1], s[2], s[3], s[4]);
+        *right = o_weno5(s[5], s[4], s[3], s[2], s[1]);
+    } else {
+        double l0, r0, l1, r1;
+        o_ppm(s[0], s[1], s[2], s[3], s[4], &l0, &r0);
+        o_ppm(s[1], s[2], s[3], s[4], s[5], &l1, &r1);
+        *left = r0;
+        *right = l1;
+    }
+}
+
+void oracle_reconstruct(const ocfg_t* c, const double* s, double* left, double* right)
+{
+    o_recon(c, s, left, right);
+}
+
+/* Flux through the face on the low side of cell (i,j,k) in direction d:
+ * reconstruction (Sec. 2.4.1; PLM with the generalized minmod slope, or the
+ * five-point WENO5 / PPM operators, which read three cells on each side),
+ * then the LLF or the HLLE flux (Sec. 2.4.2). */
 static void o_face_flux(const ocfg_t* c, const olay_t* L, const double* Pg, int d, int i, int j, int k,
                         double* F)
 {
@@ -361,11 +498,12 @@ static void o_face_flux(const ocfg_t* c, const olay_t* L, const double* Pg, int 
     double PL[NVMAX], PR[NVMAX];
     for (int v = 0; v < nv; ++v) {
         const double* a = Pg + (size_t)v * L->cells;
-        double pm2 = a[m - 2 * st], pm1 = a[m - st], p0 = a[m], pp1 = a[m + st];
-        double sl = o_gmm(pm1 - pm2, p0 - pm1, c->theta_plm);
-        double sr = o_gmm(p0 - pm1, pp1 - p0, c->theta_plm);
-        PL[v] = pm1 + 0.5 * sl;
-        PR[v] = p0 - 0.5 * sr;
+        double s6[6] = {0.0, a[m - 2 * st], a[m - st], a[m], a[m + st], 0.0};
+        if (c->recon != 0) {
+            s6[0] = a[m - 3 * st];
+            s6[5] = a[m + 2 * st];
+        }
+        o_recon(c, s6, &PL[v], &PR[v]);
     }
     double X[4];
     o_zone_X(c, L, i, j, k, X);
@@ -383,6 +521,13 @@ static void o_face_flux(const ocfg_t* c, const olay_t* L, const double* Pg, int 
     double lpL, lmL, lpR, lmR;
     o_speeds_state(c, PL, &G, &SL, d + 1, &lpL, &lmL);
     o_speeds_state(c, PR, &G, &SR, d + 1, &lpR, &lmR);
+    if (c->riemann == 1) {
+        /* HLLE: cR >= max(right-going speeds, 0), cL >= max(-left-going, 0) */
+        double cR = fmax(0.0, fmax(lpL, lpR)), cL = fmax(0.0, fmax(-lmL, -lmR));
+        for (int v = 0; v < nv; ++v)
+            F[v] = (cR * FL[v] + cL * FR[v] - cR * cL * (UR[v] - UL[v])) / (cL + cR);
+        return;
+    }
     double cmax = fmax(fmax(fabs(lpL), fabs(lmL)), fmax(fabs(lpR), fabs(lmR)));
     for (int v = 0; v < nv; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * cmax * (UR[v] - UL[v]);
 }
@@ -815,8 +960,10 @@ typedef struct {
     double expl[NVMAX];   /* -divF(P^E) + S^E(P^E)                           */
     /* EMHD: time level n */
     double theta_n, ucov_n[4], u0_n, qt_n, dpt_n;
-    /* EMHD: quantities frozen at P^E */
+    /* EMHD: quantities frozen at P^E, with the stage's relaxation time and
+     * diffusivities (o_tau_eff, o_diff_over_tau at P^E) */
     double rhoE, thetaE, u0E, qtE, dptE, bhE[4];
+    double tauE, chiE, nuE;
     oemhd_sp_t sp;
 } ozone_t;
 
@@ -851,11 +998,11 @@ static void o_zone_residual(void* ctx, const double* P, double* R)
         double bdu = 0.0;
         for (int mu = 0; mu < 4; ++mu) bdu += z->bhE[mu] * (S.ucov[mu] - z->ucov_n[mu]) / dtp;
         double divu = du0 + z->sp.sdiv_sp;
-        double q0 = -z->rhoE * c->chi * (z->bhE[0] * dtheta + z->thetaE * z->u0E * bdu + z->sp.sq_sp);
-        double dp0 = 3.0 * z->rhoE * c->nu * (z->bhE[0] * bdu + z->sp.sdp_sp - divu / 3.0);
-        double qt0 = q0 * sqrt(c->tau_R / (c->chi * z->rhoE * z->thetaE * z->thetaE));
-        double dpt0 = dp0 * sqrt(c->tau_R / (c->nu * z->rhoE * z->thetaE));
-        double tau = c->tau_R;
+        double q0 = -z->rhoE * z->chiE * (z->bhE[0] * dtheta + z->thetaE * z->u0E * bdu + z->sp.sq_sp);
+        double dp0 = 3.0 * z->rhoE * z->nuE * (z->bhE[0] * bdu + z->sp.sdp_sp - divu / 3.0);
+        double qt0 = q0 * sqrt(z->tauE / (z->chiE * z->rhoE * z->thetaE * z->thetaE));
+        double dpt0 = dp0 * sqrt(z->tauE / (z->nuE * z->rhoE * z->thetaE));
+        double tau = z->tauE;
         double Sq = z->G.gdet * (-(qt + z->qt_n) / (2.0 * tau) + qt0 / tau + 0.5 * z->qtE * divu);
         double Sd = z->G.gdet * (-(dpt + z->dpt_n) / (2.0 * tau) + dpt0 / tau + 0.5 * z->dptE * divu);
         R[QQ] -= Sq;
@@ -868,11 +1015,19 @@ static void o_zone_residual(void* ctx, const double* P, double* R)
  * EMHD).  B is held at its explicit update, the root of the induction rows,
  * which depend on B alone; the system is the residual's non-magnetic rows. */
 static const int o_unknown[7] = {RHO, UU, U1, U2, U3, QQ, DP};
+/* With full_system = 1 the unknowns are every primitive (an 8x8 / 10x10
+ * system, B among them, still started from its explicit update): the same
+ * root, since the B rows depend on B alone and are solved by that update. */
+static const int o_all[NVMAX] = {RHO, UU, U1, U2, U3, B1, B2, B3, QQ, DP};
+
+static int o_sys_size(const ocfg_t* c) { return c->full_system ? c->nvar : c->nvar - 3; }
+static const int* o_sys_map(const ocfg_t* c) { return c->full_system ? o_all : o_unknown; }
 
 typedef struct {
     ozone_t* z;
-    double P[NVMAX]; /* full primitive vector; B entries fixed */
-    int m;           /* number of unknowns: nvar - 3 */
+    double P[NVMAX]; /* full primitive vector; entries outside the system fixed */
+    int m;           /* number of unknowns */
+    const int* map;  /* unknown i is primitive map[i] */
 } oreduced_t;
 
 static void o_reduced_residual(void* ctx, const double* x, double* R)
@@ -880,9 +1035,9 @@ static void o_reduced_residual(void* ctx, const double* x, double* R)
     oreduced_t* q = (oreduced_t*)ctx;
     double P[NVMAX], Rf[NVMAX];
     for (int v = 0; v < NVMAX; ++v) P[v] = q->P[v];
-    for (int i = 0; i < q->m; ++i) P[o_unknown[i]] = x[i];
+    for (int i = 0; i < q->m; ++i) P[q->map[i]] = x[i];
     o_zone_residual(q->z, P, Rf);
-    for (int i = 0; i < q->m; ++i) R[i] = Rf[o_unknown[i]];
+    for (int i = 0; i < q->m; ++i) R[i] = Rf[q->map[i]];
 }
 
 static void o_zone_setup(const ocfg_t* c, const double X[4], const double* Pn, const double* PE,
@@ -909,6 +1064,17 @@ static void o_zone_setup(const ocfg_t* c, const double X[4], const double* Pn, c
         o_rescaled(c, PE, &SE, &z->qtE, &z->dptE);
         for (int mu = 0; mu < 4; ++mu) z->bhE[mu] = SE.bhcon[mu];
         z->sp = *sp;
+        if (c->closure) {
+            double chi_t, nu_t;
+            o_diff_over_tau(c, PE, &chi_t, &nu_t);
+            z->tauE = o_tau_eff(c, PE, &SE);
+            z->chiE = chi_t * z->tauE;
+            z->nuE = nu_t * z->tauE;
+        } else {
+            z->tauE = c->tau_R;
+            z->chiE = c->chi;
+            z->nuE = c->nu;
+        }
     }
 }
 
@@ -958,13 +1124,14 @@ static int o_stage_core(const ocfg_t* c, const olay_t* Lp, const double* Pn, con
                 uint8_t fl = 0;
                 oreduced_t Q;
                 Q.z = &Z;
-                Q.m = nv - 3;
+                Q.m = o_sys_size(c);
+                Q.map = o_sys_map(c);
                 for (int v = 0; v < NVMAX; ++v) Q.P[v] = v < nv ? P[v] : 0.0;
-                double x[7];
-                for (int i = 0; i < Q.m; ++i) x[i] = P[o_unknown[i]];
+                double x[NVMAX];
+                for (int i = 0; i < Q.m; ++i) x[i] = P[Q.map[i]];
                 oracle_newton_generic(Q.m, o_reduced_residual, &Q, x, dtp / urho_n, c->tol, c->eps, c->eps_bt,
                                       c->k_max, c->ls_max, c->ls_safeguard, &it, &rr, &fl, &bt);
-                for (int i = 0; i < Q.m; ++i) P[o_unknown[i]] = x[i];
+                for (int i = 0; i < Q.m; ++i) P[Q.map[i]] = x[i];
                 if (!(P[RHO] > 0.0) || !(P[UU] > 0.0)) fl |= OFLAG_UNPHYSICAL;
                 if (c->floors) {
                     double r = exp(X[1]);
@@ -1108,10 +1275,12 @@ static int o_residual_core(const ocfg_t* c, const olay_t* Lp, const double* Pn, 
                 o_zone_residual(&Z, p, r);
                 for (int v = 0; v < nv; ++v) R[(size_t)v * nz + z] = r[v];
                 if (rnorm) {
-                    /* the Newton norm: over the system rows (B rows excluded) */
-                    double rs[7];
-                    for (int i = 0; i < nv - 3; ++i) rs[i] = r[o_unknown[i]];
-                    rnorm[z] = o_norm(nv - 3, rs, dtp / Z.Un[RHO]);
+                    /* the Newton norm: over the system rows (without the B
+                     * rows unless the system is the full one) */
+                    double rs[NVMAX];
+                    const int* map = o_sys_map(c);
+                    for (int i = 0; i < o_sys_size(c); ++i) rs[i] = r[map[i]];
+                    rnorm[z] = o_norm(o_sys_size(c), rs, dtp / Z.Un[RHO]);
                 }
             }
     free(divF);
@@ -1358,6 +1527,7 @@ int oracle_system_jacobians_ghosted(const ocfg_t* c, const double* Pn, const dou
                 oreduced_t Q;
                 Q.z = &Z;
                 Q.m = m;
+                Q.map = o_unknown;
                 for (int v = 0; v < NVMAX; ++v) Q.P[v] = v < nv ? P[(size_t)v * nz + z] : 0.0;
                 double x[7], R[7];
                 for (int i = 0; i < m; ++i) x[i] = Q.P[o_unknown[i]];

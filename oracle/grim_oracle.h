@@ -41,6 +41,18 @@ typedef struct {
     int floors;            /* 1: rho >= rho_fl r^-3/2, u >= u_fl r^-5/2        */
     double rho_fl, u_fl;
     int nthreads;          /* OpenMP threads, 0 = runtime default             */
+    int full_system;       /* 0: Newton over the non-magnetic unknowns (5x5 /
+                              7x7, Sec. 8.2); 1: over all nvar primitives     */
+    int riemann;           /* 0 LLF, 1 HLLE (Sec. 2.4.2)                       */
+    int recon;             /* 0 PLM (generalized minmod), 1 WENO5, 2 PPM
+                              (Sec. 2.3; the last two need ng >= 3)          */
+    int closure;           /* 0: chi, nu as given; 1: chi = phi cs^2 tau_R,
+                              nu = psi cs^2 tau_R (Sec. 4, closing paragraph) */
+    double phi, psi;
+    int dp_saturation;     /* 1: tau_R reduced smoothly where DeltaP leaves
+                              [-b^2, b^2/2] (Sec. 8.1 firehose, Sec. 9); needs
+                              closure = 1                                    */
+    double sat_width;      /* relative overshoot that halves tau_R            */
 } ocfg_t;
 
 typedef struct {
@@ -61,6 +73,10 @@ typedef struct {
 #define OFLAG_UNPHYSICAL    8
 #define OFLAG_NONFINITE     16
 
+/* Face states of one variable between cells i-1 and i from the values of
+ * cells i-3..i+2 (s[0..5]; PLM reads s[1..4]) with the configured
+ * reconstruction. */
+void   oracle_reconstruct(const ocfg_t* c, const double* s, double* left, double* right);
 int    oracle_stage(const ocfg_t* c, const double* Pn, const double* PE,
                     double dtp, const double* guess, double* Pout,
                     int32_t* iters, double* resid, uint8_t* flags);

@@ -41,6 +41,8 @@ class OCfg(C.Structure):
         ("k_max", C.c_int), ("ls_max", C.c_int), ("ls_safeguard", C.c_int),
         ("floors", C.c_int), ("rho_fl", C.c_double), ("u_fl", C.c_double),
         ("nthreads", C.c_int),
+        ("full_system", C.c_int), ("riemann", C.c_int), ("recon", C.c_int), ("closure", C.c_int),
+        ("phi", C.c_double), ("psi", C.c_double), ("dp_saturation", C.c_int), ("sat_width", C.c_double),
     ]
 
 
@@ -107,6 +109,18 @@ def cfg_from_dict(d: dict) -> OCfg:
     c.rho_fl = d.get("rho_floor", 1e-5)
     c.u_fl = d.get("u_floor", 1e-7)
     c.nthreads = d.get("nthreads", 0)
+    c.full_system = 1 if d.get("system", "reduced") == "full" else 0
+    c.riemann = {"llf": 0, "hlle": 1}[d.get("riemann", "llf")]
+    c.recon = {"plm": 0, "weno5": 1, "ppm": 2}[d.get("recon", "plm")]
+    c.closure = 1 if d.get("closure", False) else 0
+    c.phi = d.get("phi", 1.0)
+    c.psi = d.get("psi", 1.0)
+    c.dp_saturation = 1 if d.get("dp_saturation", False) else 0
+    c.sat_width = d.get("sat_width", 0.1)
+    if c.recon != 0 and c.ng < 3:
+        raise ValueError("WENO5 and PPM read three cells on each side of a face: ng >= 3")
+    if c.dp_saturation and not c.closure:
+        raise ValueError("DeltaP saturation scales the diffusivities through the closure: closure must be on")
     return c
 
 
@@ -123,6 +137,7 @@ class Oracle:
             L = C.CDLL(_LIB)
             P = C.POINTER(OCfg)
             L.oracle_stage.argtypes = [P, _D, _D, C.c_double, _D, _D, _I32, _D, _U8]
+            L.oracle_reconstruct.argtypes = [P, _D, _D, _D]
             L.oracle_stage_ghosted.argtypes = [P, _D, _D, C.c_double, _D, _D, _I32, _D, _U8, _I32]
             L.oracle_step.argtypes = [P, _D, C.c_double, C.POINTER(OStats)]
             L.oracle_run.argtypes = [P, _D, C.c_double, C.c_int, C.POINTER(OStats)]
@@ -254,6 +269,14 @@ class Oracle:
         rc = self.L.oracle_zone_jacobian(C.byref(self.cfg), _dp(Pn), _dp(PE), dtp, _dp(P), z, _dp(J), _dp(R))
         assert rc == 0
         return J, R
+
+    def reconstruct(self, s6):
+        """(left, right) states at the face between cells i-1 and i from the
+        values of cells i-3..i+2."""
+        a = np.ascontiguousarray(s6, dtype=np.float64)
+        lo, hi = C.c_double(), C.c_double()
+        self.L.oracle_reconstruct(C.byref(self.cfg), _dp(a), C.byref(lo), C.byref(hi))
+        return lo.value, hi.value
 
     def cfl_dt(self, P, cfl):
         return float(self.L.oracle_cfl_dt(C.byref(self.cfg), _dp(self._arr(P)), cfl))

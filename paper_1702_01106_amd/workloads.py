@@ -181,6 +181,22 @@ def table1_mode(wl: dict, t: float = 0.0, amp: float = 1e-8):
     return P
 
 
+def firehose_1d(wl: dict, alpha: float = 1e-4, dP: float = -0.011):
+    """Firehose-unstable Alfven mode (Sec. 8.1, firehose test): rho = 1, u = 2,
+    u^2 = A sin(2 pi x^1), B = (0.1, B cos(2 pi x^1), 0), DeltaP = dP, with
+    A = 0.1628 alpha and B = 0.9867 alpha (the paper prints cos(2 pi x^2)
+    for B^2; the mode varies along x^1)."""
+    P = _empty(wl)
+    X1, _, _ = zone_centres(wl)
+    P[0] = 1.0
+    P[1] = 2.0
+    P[3] = 0.1628 * alpha * np.sin(2.0 * np.pi * X1)
+    P[5] = 0.1
+    P[6] = 0.9867 * alpha * np.cos(2.0 * np.pi * X1)
+    P[9] = dP
+    return P
+
+
 # ---------------------------------------------------------------- Kerr torus
 #
 # Initial data only: these Boyer-Lindquist / Kerr-Schild formulas build the
