@@ -70,6 +70,14 @@ extern "C" {
 #define GRIM_MLP_HIDDEN 128
 #define GRIM_MLP_OUT 16
 #define GRIM_MLP_PARAMS 22880
+/* Newton system, Riemann solver, reconstruction */
+#define GRIM_SYSTEM_REDUCED 0
+#define GRIM_SYSTEM_FULL 1
+#define GRIM_RIEMANN_LLF 0
+#define GRIM_RIEMANN_HLLE 1
+#define GRIM_RECON_PLM 0
+#define GRIM_RECON_WENO5 1
+#define GRIM_RECON_PPM 2
 /* per-zone flags */
 #define GRIM_FLAG_NOT_CONVERGED 1
 #define GRIM_FLAG_LS_EXHAUSTED 2
@@ -86,7 +94,8 @@ typedef struct grim_ctx grim_ctx_t;
 typedef struct {
     int ndim;            /* 1, 2 or 3 active directions                      */
     int n1, n2, n3;      /* interior zones per direction (1 if inactive)     */
-    int ng;              /* ghost layers per side of active directions (2)   */
+    int ng;              /* ghost layers per side of active directions: 2, or
+                            3 for the five-point reconstructions            */
     int model;           /* GRIM_IDEAL_MHD or GRIM_EMHD                      */
     int metric;          /* GRIM_MINKOWSKI or GRIM_MKS_KERR                  */
     double x_start[3];   /* domain in X^i (Sec. 2.1)                         */
@@ -122,6 +131,26 @@ typedef struct {
                             Minkowski grids: 0 chooses (512 while every tile
                             fits the device at once, else 256), 256 or 512
                             forces that size (for tests of both)             */
+    int full_system;     /* GRIM_SYSTEM_REDUCED: Newton over the non-magnetic
+                            primitives, B at its explicit update (5x5 / 7x7,
+                            Sec. 8.2); GRIM_SYSTEM_FULL: over all nvar
+                            primitives (8x8 / 10x10), B started at that update.
+                            The same root.                                   */
+    int riemann;         /* GRIM_RIEMANN_LLF or GRIM_RIEMANN_HLLE (Sec. 2.4.2) */
+    int recon;           /* GRIM_RECON_PLM (generalized minmod), _WENO5 or _PPM
+                            (Sec. 2.3, 2.4.1); the last two read three cells on
+                            each side of a face: ng = 3 required              */
+    int closure;         /* 0: chi and nu are the constants above; 1: per
+                            state, chi = phi cs^2 tau_R and nu = psi cs^2 tau_R
+                            (Sec. 4, closing paragraph), chi and nu unused    */
+    double phi, psi;     /* closure constants (> 0 with closure = 1)          */
+    int dp_saturation;   /* 1 (needs closure = 1): each zone's tau_R, taken at
+                            P^E, is reduced smoothly where DeltaP passes the
+                            firehose threshold -b^2 or the mirror threshold
+                            b^2/2 (Sec. 8.1, Sec. 9): with x the anisotropy
+                            over its threshold, tau = tau_R / (1 + ((x - 1) /
+                            sat_width)^2) for x > 1, at least 1e-6 tau_R    */
+    double sat_width;    /* > 0 with dp_saturation = 1                        */
 } grim_config_t;
 
 /* Per-call solver statistics (a13).  mean_iters is per zone per stage. */

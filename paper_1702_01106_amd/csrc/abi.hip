@@ -193,7 +193,18 @@ int validate(const grim_config_t* g, std::string& why)
         if (d < g->ndim && n[d] < 1) return why = "active direction with no zones", 1;
         if (d >= g->ndim && n[d] != 1) return why = "inactive direction must have n = 1", 1;
     }
-    if (g->ng != 2) return why = "ng must be 2 (PLM and flux-CT stencils)", 1;
+    if (g->ng != 2 && g->ng != 3) return why = "ng must be 2 or 3", 1;
+    if (g->recon < GRIM_RECON_PLM || g->recon > GRIM_RECON_PPM) return why = "unknown reconstruction", 1;
+    if (g->recon != GRIM_RECON_PLM && g->ng < 3)
+        return why = "WENO5 and PPM read three cells on each side of a face: ng = 3", 1;
+    if (g->riemann != GRIM_RIEMANN_LLF && g->riemann != GRIM_RIEMANN_HLLE) return why = "unknown Riemann solver", 1;
+    if (g->full_system != 0 && g->full_system != 1) return why = "full_system must be 0 or 1", 1;
+    if (g->closure != 0 && g->closure != 1) return why = "closure must be 0 or 1", 1;
+    if (g->dp_saturation != 0 && g->dp_saturation != 1) return why = "dp_saturation must be 0 or 1", 1;
+    if (g->dp_saturation && !g->closure) return why = "dp_saturation needs closure = 1", 1;
+    if (g->dp_saturation && !(g->sat_width > 0)) return why = "sat_width must be positive", 1;
+    if (g->full_system && (g->riemann || g->recon || (g->model == GRIM_EMHD && (g->closure || g->dp_saturation))))
+        return why = "the full system runs the plain method (LLF, PLM, constant chi and nu)", 1;
     if (g->model != GRIM_IDEAL_MHD && g->model != GRIM_EMHD) return why = "model must be 8 or 10", 1;
     if (g->metric != GRIM_MINKOWSKI && g->metric != GRIM_MKS_KERR) return why = "unknown metric", 1;
     if (g->metric == GRIM_MKS_KERR && g->ndim < 2) return why = "Kerr needs ndim >= 2", 1;
@@ -201,11 +212,15 @@ int validate(const grim_config_t* g, std::string& why)
         if (g->bc[d] < 0 || g->bc[d] > 2) return why = "unknown boundary condition", 1;
         if (g->bc[d] == GRIM_BC_POLAR && d != 1) return why = "polar boundary only in X2", 1;
         if (d < g->ndim && !(g->x_end[d] > g->x_start[d])) return why = "empty domain", 1;
-        if (d < g->ndim && n[d] < 2) return why = "active directions need n >= 2 (ghost maps read interior)", 1;
+        if (d < g->ndim && n[d] < g->ng)
+            return why = "active directions need n >= ng (ghost maps read interior)", 1;
     }
     if (!(g->gamma > 1.0)) return why = "gamma must exceed 1", 1;
-    if (g->model == GRIM_EMHD && !(g->tau_R > 0 && g->chi > 0 && g->nu > 0))
-        return why = "EMHD needs tau_R, chi, nu > 0", 1;
+    if (g->model == GRIM_EMHD && !(g->tau_R > 0)) return why = "EMHD needs tau_R > 0", 1;
+    if (g->model == GRIM_EMHD && !g->closure && !(g->chi > 0 && g->nu > 0))
+        return why = "EMHD needs chi, nu > 0", 1;
+    if (g->model == GRIM_EMHD && g->closure && !(g->phi > 0 && g->psi > 0))
+        return why = "the closure needs phi, psi > 0", 1;
     if (!(g->tol > 0) || !(g->eps_fd > 0) || !(g->eps_bt >= 0)) return why = "bad tolerances", 1;
     // the solver statistics pack per-wave sums into 21-bit fields
     if (g->k_max < 0 || g->k_max > 100 || g->ls_max < 1 || g->ls_max > 64)
@@ -252,12 +267,19 @@ Phys phys_of(const grim_config_t* cfg)
     ph.chi = cfg->chi;
     ph.nu = cfg->nu;
     ph.theta = cfg->plm_theta;
-    if (cfg->model == GRIM_EMHD) {
+    if (cfg->model == GRIM_EMHD && !cfg->closure) {
         ph.kq = std::sqrt(cfg->tau_R / cfg->chi);
         ph.kd = std::sqrt(cfg->tau_R / cfg->nu);
         ph.vq2 = (cfg->gamma - 1.0) * cfg->chi / cfg->tau_R;
         ph.vd2 = 4.0 * cfg->nu / (3.0 * cfg->tau_R);
     }
+    ph.closure = cfg->model == GRIM_EMHD ? cfg->closure : 0;
+    ph.phi = cfg->phi;
+    ph.psi = cfg->psi;
+    ph.sat = cfg->model == GRIM_EMHD ? cfg->dp_saturation : 0;
+    ph.sat_w = cfg->sat_width;
+    ph.riemann = cfg->riemann;
+    ph.recon = cfg->recon;
     return ph;
 }
 
@@ -340,7 +362,8 @@ bool fused_rhs(const grim_ctx* c) { return c->cfg.metric == GRIM_MINKOWSKI; }
 // Newton kernels at 256^2, and 71 against 91 us at 512^2.
 bool tiled_stage(const grim_ctx* c)
 {
-    return fused_rhs(c) && c->cfg.ndim <= 2;
+    // the tiled kernel runs the plain method (PLM: its P^E halo is two cells)
+    return fused_rhs(c) && c->cfg.ndim <= 2 && !grim::uses_options(c->ph);
 }
 
 StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp)
@@ -359,6 +382,7 @@ StageArgs stage_args(grim_ctx* c, const double* Pn, const double* PE, double dtp
     a.coef = c->coef;
     a.dtp = dtp;
     a.floors = c->cfg.floors;
+    a.full = c->cfg.full_system;
     a.rho_fl = c->cfg.rho_floor;
     a.u_fl = c->cfg.u_floor;
     return a;
@@ -376,6 +400,7 @@ NewtonArgs newton_args(grim_ctx* c, const StageArgs& s)
     a.k_max = c->cfg.k_max;
     a.ls_max = c->cfg.ls_max;
     a.ls_safeguard = c->cfg.ls_safeguard;
+    a.full = c->cfg.full_system;
     a.iters = c->iters;
     a.resid = c->resid;
     a.flags = c->flags;

@@ -76,7 +76,33 @@ struct Phys {
     double vq2, vd2; // (gamma-1) chi/tau_R, 4 nu/(3 tau_R) (Sec. 4.1)
     double tau, chi, nu;
     double theta;    // generalized-minmod parameter
+    int closure;     // 1: chi = phi cs^2 tau_R, nu = psi cs^2 tau_R per state (Sec. 4)
+    int sat;         // 1: DeltaP saturation through tau_R (Sec. 8.1, 9)
+    double phi, psi, sat_w;
+    int riemann;     // 0 LLF, 1 HLLE
+    int recon;       // 0 PLM, 1 WENO5, 2 PPM
 };
+
+// Whether a configuration uses any option beyond the plain method (HLLE, a
+// five-point reconstruction, the closure, the DeltaP saturation).  Kernels
+// are instantiated for X = false (plain) and X = true; a plain instance
+// clears the option fields of its own copy of Phys, so every option branch
+// folds away at compile time and its registers match the method without
+// options.
+__host__ __device__ inline bool uses_options(const Phys& ph)
+{
+    return ph.closure || ph.sat || ph.riemann || ph.recon;
+}
+template <bool X>
+__device__ __forceinline__ void plain_options(Phys& ph)
+{
+    if constexpr (!X) {
+        ph.closure = 0;
+        ph.sat = 0;
+        ph.riemann = 0;
+        ph.recon = 0;
+    }
+}
 
 // ---------------------------------------------------------------- geometry
 
@@ -247,15 +273,44 @@ __device__ __forceinline__ void trow(const double* P, const St<NV>& s, double* T
     }
 }
 
+// Sound speed squared cs^2 = gamma (gamma-1) u / (rho + gamma u) (Sec. 4.1).
+__device__ __forceinline__ double sound2(const double* P, const Phys& ph)
+{
+    return ph.gam * ph.gm1 * P[UU] * rcp_nr(P[RHO] + ph.gam * P[UU]);
+}
+
 // EMHD rescaled variables (eqs. q and dP): qt = q sqrt(tau/(chi rho Theta^2)),
 // DPt = DP sqrt(tau/(nu rho Theta)), Theta = P/rho; written as
-// qt = q sqrt(tau/chi) sqrt(rho)/P and DPt = DP sqrt(tau/nu)/sqrt(P).
+// qt = q sqrt(tau/chi) sqrt(rho)/P and DPt = DP sqrt(tau/nu)/sqrt(P).  With
+// the closure (chi = phi cs^2 tau, nu = psi cs^2 tau of the state itself)
+// sqrt(tau/chi) = 1/sqrt(phi cs^2) and sqrt(tau/nu) = 1/sqrt(psi cs^2).
 template <int NV>
 __device__ __forceinline__ void rescaled(const double* P, const St<NV>& s, const Phys& ph, double& qt, double& dpt)
 {
     const double isp = rsq_nr(s.pg);  // 1/sqrt(P)
-    qt = P[QQ] * ph.kq * sqrt_nr(P[RHO]) * (isp * isp);
-    dpt = P[DP] * ph.kd * isp;
+    if (ph.closure) {
+        const double cs2 = sound2(P, ph);
+        qt = P[QQ] * rsq_nr(ph.phi * cs2) * sqrt_nr(P[RHO]) * (isp * isp);
+        dpt = P[DP] * rsq_nr(ph.psi * cs2) * isp;
+    } else {
+        qt = P[QQ] * ph.kq * sqrt_nr(P[RHO]) * (isp * isp);
+        dpt = P[DP] * ph.kd * isp;
+    }
+}
+
+// The relaxation time of a zone's stage at P^E (state P, derived s): tau_R,
+// or with saturation tau_R / (1 + ((x - 1)/w)^2) where the anisotropy x =
+// -DP/b^2 (DP < 0) or 2 DP/b^2 (DP > 0) exceeds 1 (firehose and mirror
+// thresholds, Sec. 8.1 and 9), at least 1e-6 tau_R; b^2 floored at 1e-30.
+template <int NV>
+__device__ __forceinline__ double tau_eff(const double* P, const St<NV>& s, const Phys& ph)
+{
+    if (!ph.sat) return ph.tau;
+    const double ib2 = rcp_nr(fmax(s.bsq, 1e-30));
+    const double x = P[DP] < 0.0 ? -P[DP] * ib2 : 2.0 * P[DP] * ib2;
+    const double y = (x - 1.0) * rcp_nr(ph.sat_w);
+    const double f = x > 1.0 ? fmax(rcp_nr(1.0 + y * y), 1e-6) : 1.0;
+    return ph.tau * f;
 }
 
 // Conserved vector U (Sec. 4: sqrt(-g) times rho u^0, T^0_nu, B^i, qt u^0, DPt u^0).
@@ -301,6 +356,8 @@ __device__ __forceinline__ void flux(const double* P, const G& g, const St<NV>& 
 }
 
 // v_max^2 (Sec. 4.1, eq. modcs).
+// With the closure vq^2 = (gamma-1) phi cs^2 and vdP^2 = 4 psi cs^2/3 of the
+// state; otherwise the constants (gamma-1) chi/tau_R and 4 nu/(3 tau_R).
 template <int NV>
 __device__ __forceinline__ double vmax2(const double* P, const St<NV>& s, const Phys& ph)
 {
@@ -308,7 +365,14 @@ __device__ __forceinline__ double vmax2(const double* P, const St<NV>& s, const 
     const double cs2 = ph.gam * ph.gm1 * P[UU] * rcp_nr(e);
     const double va2 = s.bsq * rcp_nr(e + s.bsq);
     double ct2 = cs2;
-    if constexpr (NV == 10) ct2 = 0.5 * (cs2 + ph.vq2 + sqrt_nr(cs2 * cs2 + ph.vq2 * ph.vq2)) + ph.vd2;
+    if constexpr (NV == 10) {
+        if (ph.closure) {
+            const double vq2 = ph.gm1 * ph.phi * cs2;
+            ct2 = 0.5 * (cs2 + vq2 + sqrt_nr(cs2 * cs2 + vq2 * vq2)) + (4.0 / 3.0) * ph.psi * cs2;
+        } else {
+            ct2 = 0.5 * (cs2 + ph.vq2 + sqrt_nr(cs2 * cs2 + ph.vq2 * ph.vq2)) + ph.vd2;
+        }
+    }
     return ct2 + va2 - ct2 * va2;
 }
 
@@ -330,12 +394,75 @@ __device__ __forceinline__ double cmax(const double* P, const G& g, const St<NV>
     return (fabs(B) + sqrt_nr(disc)) * rcp_nr(2.0 * fabs(A));
 }
 
+// Both grid-frame speeds along DIR of waves at +-v_max in the fluid frame
+// (the roots of the quadratic of cmax; A > 0 for any timelike u):
+// lp = (-B + sqrt(disc)) / (2A) >= lm = (-B - sqrt(disc)) / (2A).
+template <int NV, int DIR, class G>
+__device__ __forceinline__ void speeds(const double* P, const G& g, const St<NV>& s, const Phys& ph, double& lp,
+                                       double& lm)
+{
+    const double v2 = vmax2<NV>(P, s, ph);
+    const double a = 1.0 - v2;
+    const double u0 = s.ucon[0], ud = s.ucon[DIR];
+    const double A = a * u0 * u0 - v2 * g.gcon(0, 0);
+    double B = a * u0 * ud;
+    if (G::nzn(0, DIR)) B -= v2 * g.gcon(0, DIR);
+    B *= -2.0;
+    const double C = a * ud * ud - v2 * g.gcon(DIR, DIR);
+    const double sq = sqrt_nr(fmax(B * B - 4.0 * A * C, 0.0));
+    const double i2a = rcp_nr(2.0 * A);
+    lp = (sq - B) * i2a;
+    lm = (-B - sq) * i2a;
+}
+
 // Generalized minmod slope minmod(theta a, (a+b)/2, theta b) (Sec. 2.3, 2.4.1).
 __device__ __forceinline__ double gmm(double a, double b, double th)
 {
     const double x = th * a, y = 0.5 * (a + b), z = th * b;
     const double mn = fmin(x, fmin(y, z)), mx = fmax(x, fmax(y, z));
     return mn > 0.0 ? mn : (mx < 0.0 ? mx : 0.0);
+}
+
+// WENO5 (Jiang and Shu's fifth-order weighted interpolation, one of the two
+// five-point schemes Sec. 2.3 names): the value at the right face of the
+// middle cell of a..e, the weighted mean of the third-order values of the
+// stencils (a,b,c), (b,c,d), (c,d,e) with ideal weights 1/10, 6/10, 3/10,
+// their smoothness indicators and epsilon = 1e-6.
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e)
+{
+    const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+    const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+    const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+    const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+    const double t1 = b - 2.0 * c + d, u1 = b - d;
+    const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+    const double s0 = 1e-6 + (13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0;
+    const double s1 = 1e-6 + (13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1;
+    const double s2 = 1e-6 + (13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2;
+    const double w0 = 0.1 * rcp_nr(s0 * s0), w1 = 0.6 * rcp_nr(s1 * s1), w2 = 0.3 * rcp_nr(s2 * s2);
+    return (w0 * q0 + w1 * q1 + w2 * q2) * rcp_nr(w0 + w1 + w2);
+}
+
+// PPM (Colella and Woodward's piecewise parabolic method, the other scheme
+// Sec. 2.3 names): the left and right face values of the middle cell of
+// a..e.  Face values start as 7/12 (sum of the two neighbours) - 1/12 (sum of
+// the next two), bounded by the neighbouring cell values; at a local
+// extremum both become the cell value, and a parabola that would overshoot
+// has its far face value moved so that the extremum sits on the near face.
+__device__ __forceinline__ void ppm(double a, double b, double c, double d, double e, double& l, double& r)
+{
+    l = (7.0 / 12.0) * (b + c) - (1.0 / 12.0) * (a + d);
+    r = (7.0 / 12.0) * (c + d) - (1.0 / 12.0) * (b + e);
+    l = fmin(fmax(l, fmin(b, c)), fmax(b, c));
+    r = fmin(fmax(r, fmin(c, d)), fmax(c, d));
+    const double dd = r - l, m6 = 6.0 * (c - 0.5 * (l + r));
+    const bool flat = (r - c) * (c - l) <= 0.0;
+    const bool lo = !flat && dd * m6 > dd * dd;
+    const bool hi = !flat && !lo && -dd * dd > dd * m6;
+    const double l2 = flat ? c : (lo ? 3.0 * c - 2.0 * r : l);
+    const double r2 = flat ? c : (hi ? 3.0 * c - 2.0 * l : r);
+    l = l2;
+    r = r2;
 }
 
 }  // namespace grim

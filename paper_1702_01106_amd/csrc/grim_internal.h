@@ -160,6 +160,7 @@ struct StageArgs {
     double* coef;       // [kEmhdCoef][nz] (EMHD)
     double dtp;
     int floors;
+    int full;           // Newton over all nvar primitives (else the non-magnetic ones)
     double rho_fl, u_fl;
     // optional outputs of the explicit stage (test hook), [nvar][nz] / [nz][3]
     double* dbg_divF;
@@ -182,6 +183,7 @@ struct NewtonArgs {
     double tol, eps, eps_bt;
     int k_max, ls_max;
     int ls_safeguard;      // 1: each new lambda kept in [0.1, 0.5] of the previous
+    int full;              // 1: the 8x8 / 10x10 system (B among the unknowns)
     int32_t* backtracks;   // if set: rejected line-search trials per zone
     // 0: one solve; 1: FP32 pass that marks failed zones kFlagRetry instead
     // of counting them; 2: FP64 solve from P_n of the marked zones only

@@ -10,31 +10,66 @@
 
 namespace grim {
 
-// LLF flux of every variable through one face normal to DIR (Sec. 2.4):
-// left/right states by generalized-minmod PLM of the four P^E cells along DIR
-// around the face, c_max the largest |speed| of either state.  cell(v, o) is
-// variable v of the cell at offset o in {-2, -1, 0, 1} from the face's high
-// cell.  The normal B flux is exactly zero.
-template <int NV, class G, int DIR, class Cell>
+// Flux of every variable through one face normal to DIR (Sec. 2.4): left
+// and right states by reconstruction along DIR, then LLF (c_max the largest
+// |speed| of either state) or, with ph.riemann, HLLE (cR the largest
+// right-going speed and cL the largest left-going one, both at least zero).
+// cell(v, o) is variable v of the cell at offset o from the face's high
+// cell: o in {-2, -1, 0, 1} for PLM (generalized minmod), and with kFive
+// and ph.recon set also -3 and 2 for WENO5 / PPM (a grid with three ghost
+// layers).  The normal B flux is exactly zero.
+template <int NV, class G, int DIR, bool kFive = false, class Cell>
 __device__ __forceinline__ void llf_face(const Phys& ph, const G& g, const Cell& cell, double* f)
 {
     const double th = ph.theta;
     double PL[NV], PR[NV];
+    if (!kFive || ph.recon == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double pm2 = cell(v, -2), pm1 = cell(v, -1), p0 = cell(v, 0), pp1 = cell(v, 1);
-        PL[v] = pm1 + 0.5 * gmm(pm1 - pm2, p0 - pm1, th);
-        PR[v] = p0 - 0.5 * gmm(p0 - pm1, pp1 - p0, th);
+        for (int v = 0; v < NV; ++v) {
+            const double pm2 = cell(v, -2), pm1 = cell(v, -1), p0 = cell(v, 0), pp1 = cell(v, 1);
+            PL[v] = pm1 + 0.5 * gmm(pm1 - pm2, p0 - pm1, th);
+            PR[v] = p0 - 0.5 * gmm(p0 - pm1, pp1 - p0, th);
+        }
+    } else if (ph.recon == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double a = cell(v, -3), b = cell(v, -2), c = cell(v, -1), d = cell(v, 0), e = cell(v, 1),
+                         h = cell(v, 2);
+            PL[v] = weno5(a, b, c, d, e);
+            PR[v] = weno5(h, e, d, c, b);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double a = cell(v, -3), b = cell(v, -2), c = cell(v, -1), d = cell(v, 0), e = cell(v, 1),
+                         h = cell(v, 2);
+            double l0, r0, l1, r1;
+            ppm(a, b, c, d, e, l0, r0);
+            ppm(b, c, d, e, h, l1, r1);
+            PL[v] = r0;
+            PR[v] = l1;
+        }
     }
     St<NV> sL, sR;
     derive<NV>(PL, g, ph, sL);
     derive<NV>(PR, g, ph, sR);
-    const double c = fmax(cmax<NV, DIR>(PL, g, sL, ph), cmax<NV, DIR>(PR, g, sR, ph));
     double UL[NV], UR[NV], FL[NV], FR[NV];
     conserved<NV>(PL, g, sL, ph, UL);
     conserved<NV>(PR, g, sR, ph, UR);
     flux<NV, DIR>(PL, g, sL, ph, FL);
     flux<NV, DIR>(PR, g, sR, ph, FR);
+    if (ph.riemann) {
+        double lpL, lmL, lpR, lmR;
+        speeds<NV, DIR>(PL, g, sL, ph, lpL, lmL);
+        speeds<NV, DIR>(PR, g, sR, ph, lpR, lmR);
+        const double cR = fmax(0.0, fmax(lpL, lpR)), cL = fmax(0.0, fmax(-lmL, -lmR));
+        const double is = rcp_nr(cL + cR), cRL = cR * cL;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            f[v] = (v == B1 + DIR - 1) ? 0.0 : (cR * FL[v] + cL * FR[v] - cRL * (UR[v] - UL[v])) * is;
+        return;
+    }
+    const double c = fmax(cmax<NV, DIR>(PL, g, sL, ph), cmax<NV, DIR>(PR, g, sR, ph));
 #pragma unroll
     for (int v = 0; v < NV; ++v) f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
 }
@@ -272,19 +307,32 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         sdiv = divs + gdv;
         sdp = b1 - gb;
 
-        // fold the P-independent parts of the relaxation sources
+        // fold the P-independent parts of the relaxation sources, with the
+        // stage's relaxation time and diffusivities taken at P^E: tau_R (or
+        // its saturated value) and chi, nu (or phi cs^2 tau, psi cs^2 tau of
+        // P^E with the closure, when tau/chi = 1/(phi cs^2), tau/nu =
+        // 1/(psi cs^2))
         const Phys& ph = a.ph;
         const double gd = g.gdet();
-        const double tau = ph.tau, itau = 1.0 / tau;
         const double rhoE = PE[RHO], thE = sE.pg * rcp_nr(PE[RHO]), u0E = sE.ucon[0];
         double qtE, dptE, qtn, dptn;
         rescaled<NV>(PE, sE, ph, qtE, dptE);
         rescaled<NV>(Pn, sn, ph, qtn, dptn);
+        double tau = ph.tau, chiE = ph.chi, nuE = ph.nu, kq = ph.kq, kd = ph.kd;
+        if (ph.closure) {
+            const double cs2 = sound2(PE, ph);
+            tau = tau_eff<NV>(PE, sE, ph);
+            chiE = ph.phi * cs2 * tau;
+            nuE = ph.psi * cs2 * tau;
+            kq = rsq_nr(ph.phi * cs2);
+            kd = rsq_nr(ph.psi * cs2);
+        }
+        const double itau = 1.0 / tau;
         // sqrt(tau/(chi rho Theta^2)) and sqrt(tau/(nu rho Theta)) at P^E
-        const double kqE = ph.kq * rsq_nr(rhoE * thE * thE);
-        const double kdE = ph.kd * rsq_nr(rhoE * thE);
-        const double cq = (kqE * itau) * (-rhoE * ph.chi);
-        const double cd = (kdE * itau) * (3.0 * rhoE * ph.nu);
+        const double kqE = kq * rsq_nr(rhoE * thE * thE);
+        const double kdE = kd * rsq_nr(rhoE * thE);
+        const double cq = (kqE * itau) * (-rhoE * chiE);
+        const double cd = (kdE * itau) * (3.0 * rhoE * nuE);
         const double thn = sn.pg * rcp_nr(Pn[RHO]);
         const double u0n = sn.ucon[0];
         const double cbun = sE.bh[0] * sn.ucov[0] + sE.bh[1] * sn.ucov[1] + sE.bh[2] * sn.ucov[2] + sE.bh[3] * sn.ucov[3];
@@ -299,7 +347,7 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         co[8] = gd * cq * thE * u0E * idt;
         co[9] = gd * 0.5 * qtE * idt;
         co[10] = gd * cd * sE.bh[0] * idt;
-        co[11] = gd * (-(kdE * itau) * rhoE * ph.nu + 0.5 * dptE) * idt;
+        co[11] = gd * (-(kdE * itau) * rhoE * nuE + 0.5 * dptE) * idt;
         co[12] = gd * (0.5 * itau);
     }
     if constexpr (!kOut) return;

@@ -110,22 +110,25 @@ __device__ __forceinline__ void zone_residual(const double* P, const ZoneC<NV, G
     }
 }
 
-// The Newton system (Sec. 8.2: 5x5 for ideal MHD, 7x7 for EMHD) is over the
-// non-magnetic primitives; B stays at its explicit update, the root of the
-// induction rows, which depend on B alone.  Unknown i is primitive unk(i).
-template <int NV>
+// The Newton system.  The paper's (Sec. 8.2: 5x5 for ideal MHD, 7x7 for
+// EMHD) is over the non-magnetic primitives; B stays at its explicit update,
+// the root of the induction rows, which depend on B alone.  With FULL the
+// system is over all NV primitives (8x8 / 10x10), B started at that update:
+// the same root.  Unknown i is primitive unk<FULL>(i).
+template <int NV, bool FULL = false>
 struct Sys {
-    static constexpr int N = NV - 3;
+    static constexpr int N = FULL ? NV : NV - 3;
 };
-__device__ __forceinline__ constexpr int unk(int i) { return i < B1 ? i : i + 3; }
+template <bool FULL = false>
+__device__ __forceinline__ constexpr int unk(int i) { return FULL ? i : (i < B1 ? i : i + 3); }
 
-// sum of squares of the system rows of a residual vector (B rows excluded)
-template <int NV>
+// sum of squares of the system rows of a residual vector
+template <int NV, bool FULL = false>
 __device__ __forceinline__ double sumsq(const double* R)
 {
     double s = R[0] * R[0];
 #pragma unroll
-    for (int i = 1; i < Sys<NV>::N; ++i) s = fma(R[unk(i)], R[unk(i)], s);
+    for (int i = 1; i < Sys<NV, FULL>::N; ++i) s = fma(R[unk<FULL>(i)], R[unk<FULL>(i)], s);
     return s;
 }
 

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_ghosts(Layout L, int nvar, int 
 
 // The face on the low side of cell (i, j, k) in direction DIR (llf_face),
 // read from and stored to the stage buffers.
-template <int NV, class G, int DIR>
+template <int NV, class G, int DIR, bool X>
 __device__ __forceinline__ void face_flux(const StageArgs& a, int i, int j, int k)
 {
     const Layout& L = a.L;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void face_flux(const StageArgs& a, int i, int j, int 
     G g;
     if constexpr (!G::kFlat) load_geo(g, a.geo.face[DIR - 1], (size_t)((long)j * L.N[0] + i), a.geo.stride);
     double f[NV];
-    llf_face<NV, G, DIR>(a.ph, g, [&](int v, int o) { return a.PE[(long)v * L.cells + m + o * st]; }, f);
+    llf_face<NV, G, DIR, X>(a.ph, g, [&](int v, int o) { return a.PE[(long)v * L.cells + m + o * st]; }, f);
     double* F = a.F[DIR - 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[(long)v * L.cells + m] = f[v];
@@ -86,9 +86,10 @@ struct FaceRanges {
     unsigned first[4];
 };
 
-template <int NV, class G>
+template <int NV, class G, bool X>
 __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
 {
+    plain_options<X>(a.ph);
     // Minkowski: each XCD takes a contiguous eighth of the faces.  Kerr:
     // plane-interleaved order (plane_blocks) without the XCD renumbering, so
     // the blocks in flight on the whole device share the 2-D face metric
@@ -116,16 +117,17 @@ __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
         j = lo[1] + (int)q;
         k = lo[2] + (int)kk;
     }
-    if (d == 0) face_flux<NV, G, 1>(a, i, j, k);
-    else if (d == 1) face_flux<NV, G, 2>(a, i, j, k);
-    else face_flux<NV, G, 3>(a, i, j, k);
+    if (d == 0) face_flux<NV, G, 1, X>(a, i, j, k);
+    else if (d == 1) face_flux<NV, G, 2, X>(a, i, j, k);
+    else face_flux<NV, G, 3, X>(a, i, j, k);
 }
 
 // One thread per interior zone: the stage right-hand side (zone_rhs), stored
 // for the Newton kernel.
-template <int NV, class G, int ND>
+template <int NV, class G, int ND, bool X>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_rhs(StageArgs a)
 {
+    plain_options<X>(a.ph);
     // Kerr 3-D: column order (column_zone), the block's four waves in four
     // successive planes of one row segment, so they share its metric and
     // connection table points (5% faster on both tori than the plain order;
@@ -163,9 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_math_probe(const double* x, double* 
 
 // ------------------------------------------------------------------ residual hook
 
-template <int NV, class G>
+template <int NV, class G, bool X>
 __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a, const double* P, double* R, double* rnorm)
 {
+    plain_options<X>(a.ph);
     const long z = (long)blockIdx.x * kBlock + threadIdx.x;
     if (z >= a.L.nz) return;
     const long cell = zone_cell(a.L, z);
@@ -184,16 +187,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a, const double* 
         St<NV> sn;
         derive<NV>(pn, zc.g, a.ph, sn);
         const double urho = zc.g.gdet() * pn[RHO] * sn.ucon[0];
-        rnorm[z] = a.dtp * sqrt(sumsq<NV>(r)) / urho;
+        rnorm[z] = a.dtp * sqrt(a.full ? sumsq<NV, true>(r) : sumsq<NV, false>(r)) / urho;
     }
 }
 
 // ------------------------------------------------------------------ CFL
 
-template <int NV, class G>
+template <int NV, class G, bool X>
 __global__ __launch_bounds__(kBlock) void k_cfl(Layout L, Phys ph, GeoTables geo, const double* P,
                                                 unsigned long long* out)
 {
+    plain_options<X>(ph);
     __shared__ double red[kBlock];
     const long z = (long)blockIdx.x * kBlock + threadIdx.x;
     double t = 1e300;
@@ -308,19 +312,26 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
     }
     r.first[3] = blocks;
     for (int d = nd; d < 3; ++d) r.first[d] = blocks;
-    hipLaunchKernelGGL((k_fluxes<NV, G>), dim3(blocks), dim3(kBlock), 0, st, a, r);
+    if (uses_options(a.ph)) hipLaunchKernelGGL((k_fluxes<NV, G, true>), dim3(blocks), dim3(kBlock), 0, st, a, r);
+    else hipLaunchKernelGGL((k_fluxes<NV, G, false>), dim3(blocks), dim3(kBlock), 0, st, a, r);
+    return hipGetLastError();
+}
+
+template <int NV, class G, bool X>
+hipError_t rhs_x(const StageArgs& a, hipStream_t st)
+{
+    const bool col = !G::kFlat && a.L.ndim == 3;
+    const dim3 grid(col ? nblocks(column_waves(a.L), kBlock / 64) : nblocks(a.L.nz)), blk(kBlock);
+    if (a.L.ndim == 1) hipLaunchKernelGGL((k_rhs<NV, G, 1, X>), grid, blk, 0, st, a);
+    else if (a.L.ndim == 2) hipLaunchKernelGGL((k_rhs<NV, G, 2, X>), grid, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_rhs<NV, G, 3, X>), grid, blk, 0, st, a);
     return hipGetLastError();
 }
 
 template <int NV, class G>
 hipError_t rhs_t(const StageArgs& a, hipStream_t st)
 {
-    const bool col = !G::kFlat && a.L.ndim == 3;
-    const dim3 grid(col ? nblocks(column_waves(a.L), kBlock / 64) : nblocks(a.L.nz)), blk(kBlock);
-    if (a.L.ndim == 1) hipLaunchKernelGGL((k_rhs<NV, G, 1>), grid, blk, 0, st, a);
-    else if (a.L.ndim == 2) hipLaunchKernelGGL((k_rhs<NV, G, 2>), grid, blk, 0, st, a);
-    else hipLaunchKernelGGL((k_rhs<NV, G, 3>), grid, blk, 0, st, a);
-    return hipGetLastError();
+    return uses_options(a.ph) ? rhs_x<NV, G, true>(a, st) : rhs_x<NV, G, false>(a, st);
 }
 
 template <int NV, class G>
@@ -361,12 +372,16 @@ hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const doubl
                            hipStream_t st)
 {
     const dim3 grid(nblocks(a.L.nz)), blk(kBlock);
+    const bool x = uses_options(a.ph);
     if (nvar == 8) {
-        if (metric == 0) hipLaunchKernelGGL((k_residual<8, GeoMink>), grid, blk, 0, st, a, P, R, rnorm);
-        else hipLaunchKernelGGL((k_residual<8, GeoKS>), grid, blk, 0, st, a, P, R, rnorm);
+        if (metric == 0) hipLaunchKernelGGL((k_residual<8, GeoMink, false>), grid, blk, 0, st, a, P, R, rnorm);
+        else hipLaunchKernelGGL((k_residual<8, GeoKS, false>), grid, blk, 0, st, a, P, R, rnorm);
+    } else if (!x) {
+        if (metric == 0) hipLaunchKernelGGL((k_residual<10, GeoMink, false>), grid, blk, 0, st, a, P, R, rnorm);
+        else hipLaunchKernelGGL((k_residual<10, GeoKS, false>), grid, blk, 0, st, a, P, R, rnorm);
     } else {
-        if (metric == 0) hipLaunchKernelGGL((k_residual<10, GeoMink>), grid, blk, 0, st, a, P, R, rnorm);
-        else hipLaunchKernelGGL((k_residual<10, GeoKS>), grid, blk, 0, st, a, P, R, rnorm);
+        if (metric == 0) hipLaunchKernelGGL((k_residual<10, GeoMink, true>), grid, blk, 0, st, a, P, R, rnorm);
+        else hipLaunchKernelGGL((k_residual<10, GeoKS, true>), grid, blk, 0, st, a, P, R, rnorm);
     }
     return hipGetLastError();
 }
@@ -374,13 +389,14 @@ hipError_t launch_residual(const StageArgs& a, int nvar, int metric, const doubl
 hipError_t launch_cfl(const Layout& L, const Phys& ph, const GeoTables& geo, int nvar, int metric, const double* P,
                       unsigned long long* out_bits, hipStream_t st)
 {
+    // the time step depends on the closure (through v_max) only
     const dim3 grid(nblocks(L.nz)), blk(kBlock);
     if (nvar == 8) {
-        if (metric == 0) hipLaunchKernelGGL((k_cfl<8, GeoMink>), grid, blk, 0, st, L, ph, geo, P, out_bits);
-        else hipLaunchKernelGGL((k_cfl<8, GeoKS>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        if (metric == 0) hipLaunchKernelGGL((k_cfl<8, GeoMink, false>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        else hipLaunchKernelGGL((k_cfl<8, GeoKS, false>), grid, blk, 0, st, L, ph, geo, P, out_bits);
     } else {
-        if (metric == 0) hipLaunchKernelGGL((k_cfl<10, GeoMink>), grid, blk, 0, st, L, ph, geo, P, out_bits);
-        else hipLaunchKernelGGL((k_cfl<10, GeoKS>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        if (metric == 0) hipLaunchKernelGGL((k_cfl<10, GeoMink, true>), grid, blk, 0, st, L, ph, geo, P, out_bits);
+        else hipLaunchKernelGGL((k_cfl<10, GeoKS, true>), grid, blk, 0, st, L, ph, geo, P, out_bits);
     }
     return hipGetLastError();
 }

@@ -154,11 +154,11 @@ __device__ __forceinline__ void Pc_from_net(const double* pn, const float* y, do
 // (about -(u^0)^2) for the first pivot, a near tie that made partial
 // pivoting swap the two rows in about 40% of slow-flow zones.  Returns false
 // on an exactly zero pivot.
-template <int NV, class G, typename JT>
+template <int NV, class G, typename JT, bool FULL>
 __device__ __forceinline__ bool newton_dir(const double* P, const double* R, const ZoneC<NV, G>& zc,
                                            const Phys& ph, double eps, double* dP)
 {
-    constexpr int N = Sys<NV>::N;
+    constexpr int N = Sys<NV, FULL>::N;
 #pragma unroll
     for (int v = 0; v < NV; ++v) dP[v] = 0.0;
     JT J[N][N];
@@ -167,7 +167,7 @@ __device__ __forceinline__ bool newton_dir(const double* P, const double* R, con
         double Pe[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) Pe[q] = P[q];
-        const double pj = P[unk(j)];
+        const double pj = P[unk<FULL>(j)];
         const bool small = fabs(pj) < 5.0 * eps;
         double pe = small ? eps : (1.0 + eps) * pj;
         double h = pe - pj;
@@ -175,39 +175,42 @@ __device__ __forceinline__ bool newton_dir(const double* P, const double* R, con
             pe = pj + eps;
             h = pe - pj;
         }
-        Pe[unk(j)] = pe;
+        Pe[unk<FULL>(j)] = pe;
         double Re[NV];
         zone_residual<NV, G>(Pe, zc, ph, Re);
         const double ih = rcp_nr(h);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const double d = Re[unk(i)] - R[unk(i)];
+            const double d = Re[unk<FULL>(i)] - R[unk<FULL>(i)];
             J[i][j] = (JT)((i == 1 ? d + (Re[RHO] - R[RHO]) : d) * ih);
         }
     }
-    static_assert(unk(0) == RHO && unk(1) == UU, "mass and energy rows come first");
+    static_assert(unk<FULL>(0) == RHO && unk<FULL>(1) == UU, "mass and energy rows come first");
     JT x[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = (JT)(i == 1 ? -(R[UU] + R[RHO]) : -R[unk(i)]);
+    for (int i = 0; i < N; ++i) x[i] = (JT)(i == 1 ? -(R[UU] + R[RHO]) : -R[unk<FULL>(i)]);
     if (!lu_solve<N, JT>(J, x)) return false;
 #pragma unroll
-    for (int i = 0; i < N; ++i) dP[unk(i)] = (double)x[i];
+    for (int i = 0; i < N; ++i) dP[unk<FULL>(i)] = (double)x[i];
     return true;
 }
 
 // Ghosted coordinates along one direction that take their value from
 // ghosted index p of an interior cell: p itself and up to two ghost images,
 // the inverses of the ghost maps (periodic wrap, outflow clamp, polar mirror)
-// for Ng = 2 and n >= 2, which the host enforces.  Held in registers (an
-// array indexed by a per-lane count would be placed in LDS or scratch).
+// for n >= Ng, which the host enforces.  Held in registers (an array indexed
+// by a per-lane count would be placed in LDS or scratch).
 struct GhostSlots {
     int cnt;     // 1 + number of images
-    int q1, q2;  // the images (q2 only when cnt == 3)
+    int q1, q2;  // the images (q2 only when cnt == 3); outflow: the images
+                 // are the Ng consecutive cells from q1
+    bool run;
 };
 
 __device__ __forceinline__ GhostSlots ghost_slots(int p, int g, int n, int bc)
 {
     GhostSlots s;
+    s.run = bc == 1;
     if (bc == 0) {
         // periodic: lower ghost p - n (p >= n), upper ghost p + n (p < 2g)
         const bool lo = p >= n, hi = p < 2 * g;
@@ -215,9 +218,10 @@ __device__ __forceinline__ GhostSlots ghost_slots(int p, int g, int n, int bc)
         s.q1 = lo ? p - n : p + n;
         s.q2 = p + n;
     } else if (bc == 1) {
-        // outflow: the first interior cell fills both lower ghosts, the last both upper
+        // outflow: the first interior cell fills every lower ghost, the last
+        // every upper one
         const bool lo = p == g, hi = p == g + n - 1;
-        s.cnt = (lo || hi) ? 3 : 1;
+        s.cnt = (lo || hi) ? 1 + g : 1;
         s.q1 = lo ? 0 : g + n;
         s.q2 = s.q1 + 1;
     } else {
@@ -230,7 +234,10 @@ __device__ __forceinline__ GhostSlots ghost_slots(int p, int g, int n, int bc)
     return s;
 }
 
-__device__ __forceinline__ int slot(int a, int p, const GhostSlots& s) { return a == 0 ? p : (a == 1 ? s.q1 : s.q2); }
+__device__ __forceinline__ int slot(int a, int p, const GhostSlots& s)
+{
+    return a == 0 ? p : (s.run ? s.q1 + a - 1 : (a == 1 ? s.q1 : s.q2));
+}
 
 // Store a zone's primitives at its cell and at every ghost cell that maps to
 // it (the composite map is the product of the per-direction maps; a polar
@@ -241,7 +248,7 @@ __device__ __forceinline__ void store_with_ghosts(const Layout& L, const int* bc
 {
     const int p0 = i + L.g[0], p1 = j + L.g[1], p2 = k + L.g[2];
     const GhostSlots s0 = ghost_slots(p0, L.g[0], L.n[0], bc[0]);
-    GhostSlots s1{1, 0, 0}, s2{1, 0, 0};
+    GhostSlots s1{1, 0, 0, false}, s2{1, 0, 0, false};
     if (L.ndim > 1) s1 = ghost_slots(p1, L.g[1], L.n[1], bc[1]);
     if (L.ndim > 2) s2 = ghost_slots(p2, L.g[2], L.n[2], bc[2]);
     const bool polar = bc[1] == 2;
@@ -277,7 +284,7 @@ struct ZoneSolve {
 // B at its explicit update (the exact root of the B rows), the learned
 // candidate if one is given and its residual is smaller, and the initial
 // residual.
-template <int NV, class G, int ND, class Src = SrcGlobal>
+template <int NV, class G, int ND, bool FULL, class Src = SrcGlobal>
 __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const double* guess, const float* mlp_y,
                                          ZoneSolve<NV, G>& s, const Src* in = nullptr)
 {
@@ -325,7 +332,7 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
     for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
     zone_residual<NV, G>(s.P, s.zc, ph, s.R);
     ++s.ncalls;
-    s.r = s.nscale * sqrt_nr(sumsq<NV>(s.R));
+    s.r = s.nscale * sqrt_nr(sumsq<NV, FULL>(s.R));
     if (mlp_y) {
         // keep the learned guess only if its residual is smaller
 #pragma unroll
@@ -333,7 +340,7 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
         double Rc[NV];
         zone_residual<NV, G>(P_alt, s.zc, ph, Rc);
         ++s.ncalls;
-        const double rc = s.nscale * sqrt_nr(sumsq<NV>(Rc));
+        const double rc = s.nscale * sqrt_nr(sumsq<NV, FULL>(Rc));
         if (rc < s.r) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -352,10 +359,10 @@ __device__ __forceinline__ void zs_begin(const NewtonArgs& a, long z, const doub
 // with its line search.  Returns true once the solve has ended (converged, or
 // failed with the flags set).  A failed solve from the learned guess starts
 // again from P_n instead of ending.
-template <int NV, class G, typename JT>
+template <int NV, class G, typename JT, bool FULL>
 __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s)
 {
-    constexpr int N = Sys<NV>::N;
+    constexpr int N = Sys<NV, FULL>::N;
     const Phys& ph = a.s.ph;
     bool ended = false;
     if (!isfinite(s.r)) {
@@ -368,7 +375,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
         ended = true;
     } else {
         double dP[NV];
-        const bool ok = newton_dir<NV, G, JT>(s.P, s.R, s.zc, ph, a.eps, dP);
+        const bool ok = newton_dir<NV, G, JT, FULL>(s.P, s.R, s.zc, ph, a.eps, dP);
         s.ncalls += N;
         if (!ok) {
             s.fl |= 4;
@@ -385,7 +392,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
                 for (int v = 0; v < NV; ++v) Pt[v] = fma(lam, dP[v], s.P[v]);
                 zone_residual<NV, G>(Pt, s.zc, ph, Rt);
                 ++s.ncalls;
-                const double rt = s.nscale * sqrt_nr(sumsq<NV>(Rt));
+                const double rt = s.nscale * sqrt_nr(sumsq<NV, FULL>(Rt));
                 if (isfinite(rt)) {
                     have = true;
 #pragma unroll
@@ -441,7 +448,7 @@ __device__ __forceinline__ bool zs_step(const NewtonArgs& a, ZoneSolve<NV, G>& s
     for (int i = 0; i < 3; ++i) s.P[B1 + i] = s.zc.rhs[B1 + i] * s.fB;
     zone_residual<NV, G>(s.P, s.zc, ph, s.R);
     ++s.ncalls;
-    s.r = s.nscale * sqrt_nr(sumsq<NV>(s.R));
+    s.r = s.nscale * sqrt_nr(sumsq<NV, FULL>(s.R));
     return false;
 }
 
@@ -550,9 +557,10 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
 // work-queue variant, where a lane that finished took the next zone of its
 // wave's range, ran 20-45% slower on every workload measured and was
 // dropped.)
-template <int NV, class G, typename JT, int ND>
+template <int NV, class G, typename JT, int ND, bool FULL, bool X>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
+    plain_options<X>(a.s.ph);
     // (the plane-interleaved order of the Kerr flux kernel made this one
     // 4-6% slower on the Kerr tori)
     // (the column order of the Kerr rhs kernel, with or without the XCD
@@ -567,8 +575,8 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     LaneStats ls;
     if (active) {
         ZoneSolve<NV, G> s;
-        zs_begin<NV, G, ND>(a, z, retry ? nullptr : a.guess, retry ? nullptr : a.mlp_y, s);
-        while (!zs_step<NV, G, JT>(a, s)) {
+        zs_begin<NV, G, ND, FULL>(a, z, retry ? nullptr : a.guess, retry ? nullptr : a.mlp_y, s);
+        while (!zs_step<NV, G, JT, FULL>(a, s)) {
         }
         zs_finish<NV, G>(a, s, retry, ls);
     }
@@ -608,10 +616,23 @@ __device__ __forceinline__ void llf_pair(const Phys& ph, const GeoMink& g, const
     }
     St<NV> st;
     derive<NV>(P, g, ph, st);
-    const double c = cmax<NV, DIR>(P, g, st, ph);
     double U[NV], F[NV];
     conserved<NV>(P, g, st, ph, U);
     flux<NV, DIR>(P, g, st, ph, F);
+    if (ph.riemann) {
+        // HLLE, as llf_face: the even lane's state is the left one
+        double lp, lm;
+        speeds<NV, DIR>(P, g, st, ph, lp, lm);
+        const double cR = fmax(0.0, fmax(lp, pair_swap(lp))), cL = fmax(0.0, fmax(-lm, -pair_swap(lm)));
+        const double is = rcp_nr(cL + cR), cRL = cR * cL;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
+            f[v] = (v == B1 + DIR - 1) ? 0.0 : (cR * F[v] + cL * Fo - cRL * (Uo - U[v])) * is;
+        }
+        return;
+    }
+    const double c = cmax<NV, DIR>(P, g, st, ph);
     const double cc = fmax(c, pair_swap(c));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -670,9 +691,10 @@ struct SrcTile {
 // instead: waves 4-7 stage P^E and compute the y-faces beside waves 0-3 (the
 // x-faces), so the face phase runs two waves per SIMD, and then leave the
 // zones to waves 0-3.
-template <int NV, int ND, typename JT, int kBlock>
+template <int NV, int ND, typename JT, int kBlock, bool FULL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_stage(NewtonArgs a)
 {
+    plain_options<false>(a.s.ph);  // the tiled stage runs the plain method only
     static_assert(kBlock == Tile<ND>::kThreads || (ND == 2 && kBlock == 2 * Tile<ND>::kThreads), "block size");
     using T = Tile<ND>;
     __shared__ double lds[T::template words<NV>()];
@@ -819,8 +841,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (active) {
         const SrcTile<NV, ND> in{pe, fx, fy, pn, lx, ly};
         ZoneSolve<NV, GeoMink> s;
-        zs_begin<NV, GeoMink, ND>(a, z, a.guess, nullptr, s, &in);
-        while (!zs_step<NV, GeoMink, JT>(a, s)) {
+        zs_begin<NV, GeoMink, ND, FULL>(a, z, a.guess, nullptr, s, &in);
+        while (!zs_step<NV, GeoMink, JT, FULL>(a, s)) {
         }
         bool retried = false;
         if constexpr (!__is_same(JT, double)) {
@@ -829,8 +851,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             // a second launch); iterations and residual calls of both count
             if (s.fl & (1 | 4 | 16)) {
                 const int it = s.iters, nc = s.ncalls, nb = s.nbt;
-                zs_begin<NV, GeoMink, ND>(a, z, nullptr, nullptr, s, &in);
-                while (!zs_step<NV, GeoMink, double>(a, s)) {
+                zs_begin<NV, GeoMink, ND, FULL>(a, z, nullptr, nullptr, s, &in);
+                while (!zs_step<NV, GeoMink, double, FULL>(a, s)) {
                 }
                 s.iters += it;
                 s.ncalls += nc;
@@ -845,7 +867,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (a.stats && tid < T::kThreads) flush_stats(a, ls);  // waves 4-7 solve no zone
 }
 
-template <int NV, int ND>
+template <int NV, int ND, bool FULL>
 hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     using T = Tile<ND>;
@@ -858,16 +880,16 @@ hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
     const bool wide = ND == 2 && (a.block == 512 || (a.block == 0 && a.cus > 0 && tiles <= a.cus));
     const dim3 grid((unsigned)tiles);
     if (jac_f32) {
-        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, float, kWide>), grid, dim3(kWide), 0, st, b);
-        else hipLaunchKernelGGL((k_stage<NV, ND, float, T::kThreads>), grid, dim3(T::kThreads), 0, st, b);
+        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, float, kWide, FULL>), grid, dim3(kWide), 0, st, b);
+        else hipLaunchKernelGGL((k_stage<NV, ND, float, T::kThreads, FULL>), grid, dim3(T::kThreads), 0, st, b);
     } else {
-        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, double, kWide>), grid, dim3(kWide), 0, st, b);
-        else hipLaunchKernelGGL((k_stage<NV, ND, double, T::kThreads>), grid, dim3(T::kThreads), 0, st, b);
+        if (wide) hipLaunchKernelGGL((k_stage<NV, ND, double, kWide, FULL>), grid, dim3(kWide), 0, st, b);
+        else hipLaunchKernelGGL((k_stage<NV, ND, double, T::kThreads, FULL>), grid, dim3(T::kThreads), 0, st, b);
     }
     return hipGetLastError();
 }
 
-template <int NV, class G, int ND>
+template <int NV, class G, int ND, bool FULL, bool X>
 hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
@@ -876,14 +898,14 @@ hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
         // FP32 pass, then the FP64 retry of the zones it marks (needs flags)
         if (!a.flags) return hipErrorInvalidValue;
         b.pass = 1;
-        hipLaunchKernelGGL((k_newton<NV, G, float, ND>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, float, ND, FULL, X>), grid, blk, 0, st, b);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         b.pass = 2;
-        hipLaunchKernelGGL((k_newton<NV, G, double, ND>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, double, ND, FULL, X>), grid, blk, 0, st, b);
     } else {
         b.pass = 0;
-        hipLaunchKernelGGL((k_newton<NV, G, double, ND>), grid, blk, 0, st, b);
+        hipLaunchKernelGGL((k_newton<NV, G, double, ND, FULL, X>), grid, blk, 0, st, b);
     }
     return hipGetLastError();
 }
@@ -891,29 +913,44 @@ hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 // The fused form exists for Minkowski only: with the Kerr tables (16 metric
 // and 64 connection values per zone) the fused kernel needs more registers
 // than the Newton solve alone and loses occupancy or spills.
-template <int NV, class G>
+template <int NV, class G, bool FULL, bool X>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
     if constexpr (G::kFlat) {
-        if (a.fused && a.tiled && !a.mlp_y && a.s.L.ndim <= 2)
-            return a.s.L.ndim == 1 ? stage_tiled<NV, 1>(a, jac_f32, st) : stage_tiled<NV, 2>(a, jac_f32, st);
+        if constexpr (!X) {
+            if (a.fused && a.tiled && !a.mlp_y && a.s.L.ndim <= 2)
+                return a.s.L.ndim == 1 ? stage_tiled<NV, 1, FULL>(a, jac_f32, st)
+                                       : stage_tiled<NV, 2, FULL>(a, jac_f32, st);
+        }
         if (a.fused) {
             switch (a.s.L.ndim) {
-                case 1: return newton_nd<NV, G, 1>(a, jac_f32, st);
-                case 2: return newton_nd<NV, G, 2>(a, jac_f32, st);
-                default: return newton_nd<NV, G, 3>(a, jac_f32, st);
+                case 1: return newton_nd<NV, G, 1, FULL, X>(a, jac_f32, st);
+                case 2: return newton_nd<NV, G, 2, FULL, X>(a, jac_f32, st);
+                default: return newton_nd<NV, G, 3, FULL, X>(a, jac_f32, st);
             }
         }
     }
-    return newton_nd<NV, G, 0>(a, jac_f32, st);
+    return newton_nd<NV, G, 0, FULL, X>(a, jac_f32, st);
+}
+
+// The full system runs the plain method; a configuration with options runs
+// the paper's reduced system (the host rejects both at once).
+template <int NV, class G>
+hipError_t newton_sys(const NewtonArgs& a, int jac_f32, hipStream_t st)
+{
+    if (uses_options(a.s.ph)) {
+        if (a.full) return hipErrorInvalidValue;
+        return newton_t<NV, G, false, true>(a, jac_f32, st);
+    }
+    return a.full ? newton_t<NV, G, true, false>(a, jac_f32, st) : newton_t<NV, G, false, false>(a, jac_f32, st);
 }
 
 }  // namespace
 
 hipError_t launch_newton(const NewtonArgs& a, int nvar, int metric, int jac_f32, hipStream_t st)
 {
-    if (nvar == 8) return metric == 0 ? newton_t<8, GeoMink>(a, jac_f32, st) : newton_t<8, GeoKS>(a, jac_f32, st);
-    return metric == 0 ? newton_t<10, GeoMink>(a, jac_f32, st) : newton_t<10, GeoKS>(a, jac_f32, st);
+    if (nvar == 8) return metric == 0 ? newton_sys<8, GeoMink>(a, jac_f32, st) : newton_sys<8, GeoKS>(a, jac_f32, st);
+    return metric == 0 ? newton_sys<10, GeoMink>(a, jac_f32, st) : newton_sys<10, GeoKS>(a, jac_f32, st);
 }
 
 }  // namespace grim

@@ -39,6 +39,8 @@ class grim_config_t(C.Structure):
         ("jac_precision", C.c_int), ("guess", C.c_int),
         ("floors", C.c_int), ("rho_floor", C.c_double), ("u_floor", C.c_double),
         ("ls_safeguard", C.c_int), ("external_workspace", C.c_int), ("stage_block", C.c_int),
+        ("full_system", C.c_int), ("riemann", C.c_int), ("recon", C.c_int), ("closure", C.c_int),
+        ("phi", C.c_double), ("psi", C.c_double), ("dp_saturation", C.c_int), ("sat_width", C.c_double),
     ]
 
 
@@ -184,6 +186,14 @@ def config_from_workload(wl: dict) -> grim_config_t:
     c.ls_safeguard = int(wl.get("ls_safeguard", 0))
     c.external_workspace = 1 if wl.get("workspace", "library") == "caller" else 0
     c.stage_block = int(wl.get("stage_block", 0))
+    c.full_system = 1 if wl.get("system", "reduced") == "full" else 0
+    c.riemann = {"llf": 0, "hlle": 1}[wl.get("riemann", "llf")]
+    c.recon = {"plm": 0, "weno5": 1, "ppm": 2}[wl.get("recon", "plm")]
+    c.closure = 1 if wl.get("closure", False) else 0
+    c.phi = wl.get("phi", 1.0)
+    c.psi = wl.get("psi", 1.0)
+    c.dp_saturation = 1 if wl.get("dp_saturation", False) else 0
+    c.sat_width = wl.get("sat_width", 0.1)
     return c
 
 
