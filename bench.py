@@ -266,7 +266,8 @@ def run_forms(grim, W, wl, P0, args, names):
                                "loss_first_last": [info["loss"][0], info["loss"][-1]], "seeds": [1, 2, 3, 4]}
             log(f"{wl['name']}: trained the guess network on {info['pairs']} pairs in "
                 f"{res['training']['seconds']:.1f} s")
-        fwl = dict(wl, jac=jac, guess="mlp" if learned_guess else "pn")
+        fwl = dict(wl, jac=jac, guess="mlp" if learned_guess else "pn",
+                   system="full" if "full_system" in name else "reduced")
         w = weights if learned_guess else None
         dt, t, st, st_p, times, _ = timed_run(grim, fwl, P0, args.steps, args.warmup, weights=w)
         if value_ref is None:
@@ -534,7 +535,9 @@ def residual_probe(grim, W):
 
 # ------------------------------------------------------------------ main
 
-FORMS = ["f64", "f32_jacobian", "f64_learned_guess", "f32_jacobian_learned_guess"]
+# the plain method and its three faster forms; then the 8x8 / 10x10 system
+# (B among the unknowns), the comparison form of the paper's reduced system
+FORMS = ["f64", "f32_jacobian", "f64_learned_guess", "f32_jacobian_learned_guess", "f64_full_system"]
 
 
 def main() -> int:
@@ -600,6 +603,15 @@ def main() -> int:
         "roofline": roofline(wl, nvar, args.steps, head),
         "forms": {k: v for k, v in forms.items() if k != "f64"},
     }
+    if "f64_full_system" in forms:
+        full = forms["f64_full_system"]
+        out["system_ab"] = {
+            "reduced_zone_updates_per_s": value, "full_zone_updates_per_s": full["value"],
+            "reduced_over_full": value / full["value"],
+            "mean_iters_reduced": head["mean_newton_iters"], "mean_iters_full": full["mean_newton_iters"],
+            "newton_ms_per_step_reduced": head["kernel_ms_per_step"].get("newton"),
+            "newton_ms_per_step_full": full["kernel_ms_per_step"].get("newton"),
+        }
     variant_checks = {}
     if not args.no_variants:
         out["stream"] = stream_probe(grim, wl)
@@ -609,6 +621,8 @@ def main() -> int:
             vP0 = W.initial_state(vwl, seed=0)
             vforms, vchecks = run_forms(grim, W, vwl, vP0, args, FORMS)
             vforms["roofline"] = roofline(vwl, vwl["nvar"], args.steps, vforms["f64"])
+            vforms["system_ab"] = {"reduced_over_full": vforms["f64"]["value"] / vforms["f64_full_system"]["value"],
+                                   "mean_iters_full": vforms["f64_full_system"]["mean_newton_iters"]}
             variants[vname] = vforms
             variant_checks[vname] = {k: (vforms[k]["dt"], v) for k, v in vchecks.items()}
         out["variants"] = variants
