@@ -74,6 +74,64 @@ __device__ __forceinline__ void llf_face(const Phys& ph, const G& g, const Cell&
     for (int v = 0; v < NV; ++v) f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v]);
 }
 
+// Exchange a double with the other lane of its pair (lanes 2m and 2m + 1):
+// DPP quad permutation [1, 0, 3, 2].  Every lane of the wave must be active.
+__device__ __forceinline__ double pair_swap(double x)
+{
+    constexpr int kSwapPairs = 0xb1;
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, kSwapPairs, 0xf, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), kSwapPairs, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The LLF flux of one face normal to DIR computed by a pair of lanes (Sec.
+// 2.4): the even lane builds the left state and the odd lane the right one
+// (PLM, derived state, wave speed, U and F, each exactly as llf_face builds
+// it), the pair swaps c_max, U and F, and the even lane combines them in
+// llf_face's order; the odd lane's f is not meaningful.  cell(v, o) is as
+// for llf_face.  Every lane of the wave must take part (the swaps are
+// cross-lane).
+template <int NV, class G, int DIR, class Cell>
+__device__ __forceinline__ void llf_pair(const Phys& ph, const G& g, const Cell& cell, bool right, double* f)
+{
+    const double th = ph.theta;
+    const int o = right ? -1 : -2;
+    double P[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double x0 = cell(v, o), x1 = cell(v, o + 1), x2 = cell(v, o + 2);
+        const double h = 0.5 * gmm(x1 - x0, x2 - x1, th);
+        P[v] = right ? x1 - h : x1 + h;
+    }
+    St<NV> st;
+    derive<NV>(P, g, ph, st);
+    double U[NV], F[NV];
+    conserved<NV>(P, g, st, ph, U);
+    flux<NV, DIR>(P, g, st, ph, F);
+    if (ph.riemann) {
+        // HLLE, as llf_face: the even lane's state is the left one
+        double lp, lm;
+        speeds<NV, DIR>(P, g, st, ph, lp, lm);
+        const double cR = fmax(0.0, fmax(lp, pair_swap(lp))), cL = fmax(0.0, fmax(-lm, -pair_swap(lm)));
+        const double is = rcp_nr(cL + cR), cRL = cR * cL;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
+            f[v] = (v == B1 + DIR - 1) ? 0.0 : (cR * F[v] + cL * Fo - cRL * (Uo - U[v])) * is;
+        }
+        return;
+    }
+    const double c = cmax<NV, DIR>(P, g, st, ph);
+    const double cc = fmax(c, pair_swap(c));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
+        f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (F[v] + Fo) - 0.5 * cc * (Uo - U[v]);
+    }
+}
+
 // Where zone_rhs reads the face fluxes, P^E and P_n: F(d, v, m, o) is the
 // flux of variable v through the face normal to d on the low side of the cell
 // at offset o = (o1, o2, o3) from cell m; PE(v, m, o) is P^E there; Pn(v, m)

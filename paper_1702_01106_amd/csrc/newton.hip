@@ -583,64 +583,6 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     if (a.stats) flush_stats(a, ls);
 }
 
-// Exchange a double with the other lane of its pair (lanes 2m and 2m + 1):
-// DPP quad permutation [1, 0, 3, 2].  Every lane of the wave must be active.
-__device__ __forceinline__ double pair_swap(double x)
-{
-    constexpr int kSwapPairs = 0xb1;
-    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, kSwapPairs, 0xf, 0xf, false);
-    const unsigned hi =
-        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), kSwapPairs, 0xf, 0xf, false);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// The LLF flux of one face normal to DIR computed by a pair of lanes (Sec.
-// 2.4): the even lane builds the left state and the odd lane the right one
-// (PLM, derived state, wave speed, U and F, each exactly as llf_face builds
-// it), the pair swaps c_max, U and F, and the even lane combines them in
-// llf_face's order; the odd lane's f is not meaningful.  cell(v, o) is as
-// for llf_face.  Every lane of the wave must take part (the swaps are
-// cross-lane).
-template <int NV, int DIR, class Cell>
-__device__ __forceinline__ void llf_pair(const Phys& ph, const GeoMink& g, const Cell& cell, bool right, double* f)
-{
-    const double th = ph.theta;
-    const int o = right ? -1 : -2;
-    double P[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double x0 = cell(v, o), x1 = cell(v, o + 1), x2 = cell(v, o + 2);
-        const double h = 0.5 * gmm(x1 - x0, x2 - x1, th);
-        P[v] = right ? x1 - h : x1 + h;
-    }
-    St<NV> st;
-    derive<NV>(P, g, ph, st);
-    double U[NV], F[NV];
-    conserved<NV>(P, g, st, ph, U);
-    flux<NV, DIR>(P, g, st, ph, F);
-    if (ph.riemann) {
-        // HLLE, as llf_face: the even lane's state is the left one
-        double lp, lm;
-        speeds<NV, DIR>(P, g, st, ph, lp, lm);
-        const double cR = fmax(0.0, fmax(lp, pair_swap(lp))), cL = fmax(0.0, fmax(-lm, -pair_swap(lm)));
-        const double is = rcp_nr(cL + cR), cRL = cR * cL;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
-            f[v] = (v == B1 + DIR - 1) ? 0.0 : (cR * F[v] + cL * Fo - cRL * (Uo - U[v])) * is;
-        }
-        return;
-    }
-    const double c = cmax<NV, DIR>(P, g, st, ph);
-    const double cc = fmax(c, pair_swap(c));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double Fo = pair_swap(F[v]), Uo = pair_swap(U[v]);
-        f[v] = (v == B1 + DIR - 1) ? 0.0 : 0.5 * (F[v] + Fo) - 0.5 * cc * (Uo - U[v]);
-    }
-}
-
 // ------------------------------------------------------------------ tiled stage
 //
 // One kernel per stage for 1- and 2-D Minkowski grids: a block of 256 threads
@@ -816,13 +758,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             const int q = T::kThreads + min(e >> 1, nxf - T::kThreads - 1);
             const int cx = q % T::XX, cy = q / T::XX - T::XR;
             const double* p = pe + (cy + T::HY) * T::PX + cx + 2;
-            llf_pair<NV, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, right, f2);
+            llf_pair<NV, GeoMink, 1>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o]; }, right, f2);
             if (!right && (e >> 1) < nxf - T::kThreads) xstore(q, f2);
         } else if (tid < T::kThreads) {
             const int q = T::kThreads + min(e >> 1, nyf - T::kThreads - 1);
             const int ex = q % T::YX - 1, ey = q / T::YX;
             const double* p = pe + (ey + T::HY) * T::PX + ex + 2;
-            llf_pair<NV, 2>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o * T::PX]; }, right, f2);
+            llf_pair<NV, GeoMink, 2>(ph, g, [&](int v, int o) { return p[v * T::PY * T::PX + o * T::PX]; }, right, f2);
             if (!right && (e >> 1) < nyf - T::kThreads) ystore(q, f2);
         }
     } else {
@@ -912,7 +854,9 @@ hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 
 // The fused form exists for Minkowski only: with the Kerr tables (16 metric
 // and 64 connection values per zone) the fused kernel needs more registers
-// than the Newton solve alone and loses occupancy or spills.
+// than the Newton solve alone and spills (measured on the 192x192x96 torus:
+// 4.74 ms per step in the fused Newton kernel against 1.61 + 1.72 ms for
+// the rhs and Newton kernels).
 template <int NV, class G, bool FULL, bool X>
 hipError_t newton_t(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
