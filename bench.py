@@ -553,6 +553,7 @@ def main() -> int:
     ap.add_argument("--variant-workloads", default="emhd2d_modes_256,emhd2d_modes_512",
                     help="comma-separated other workloads for the four forms")
     ap.add_argument("--residual-probe", action="store_true", help="run the residual hook for counters and exit")
+    ap.add_argument("--stream", action="store_true", help="run the STREAM probe also with --no-variants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU halo exchange is not built",
@@ -613,8 +614,9 @@ def main() -> int:
             "newton_ms_per_step_full": full["kernel_ms_per_step"].get("newton"),
         }
     variant_checks = {}
-    if not args.no_variants:
+    if args.stream or not args.no_variants:
         out["stream"] = stream_probe(grim, wl)
+    if not args.no_variants:
         variants = {}
         for vname in [v for v in args.variant_workloads.split(",") if v and v != args.workload]:
             vwl = W.workload(vname)

@@ -151,12 +151,16 @@ def test_explicit_stage(torch_cuda, oracle_mod, name):
     gdF, gsrc, gsp = g.explicit(P)
     gdF, gsrc, gsp = gdF.cpu().numpy(), gsrc.cpu().numpy(), gsp.cpu().numpy()
     # Kerr: the two sides build g^{mu nu} independently (closed form against
-    # a numeric inverse) and difference the metric with their own code
+    # a numeric inverse) and difference the metric with their own code (the
+    # same fourth-order stencil); measured 2e-13 (divF), 1.1e-12 (source)
     kerr = name in KERR
-    tdf, tsrc = (1e-9, 1e-7) if kerr else (1e-11, 1e-12)
+    tdf, tsrc = (1e-11, 1e-10) if kerr else (1e-11, 1e-12)
     _say("  max rel err divF %.1e src %.1e" % (
         max(np.abs(gdF[v] - dF[v]).max() / max(np.abs(dF[v]).max(), 1e-300) for v in range(wl["nvar"])),
         np.abs(gsrc - src).max() / max(np.abs(src).max(), 1.0)))
+    if wl["nvar"] == 10:
+        _say("  max rel err EMHD source parts " + " ".join(
+            "%.1e" % (np.abs(gsp[:, q] - sp[:, q]).max() / max(np.abs(sp[:, q]).max(), 1e-300)) for q in range(3)))
     # divF is a difference of face fluxes that can cancel to far below the
     # fluxes themselves: besides the relative bound, allow rounding of the
     # face fluxes, 32 ulps of max|F| per unit of 1/dx
@@ -170,7 +174,7 @@ def test_explicit_stage(torch_cuda, oracle_mod, name):
     if wl["nvar"] == 10:
         for q in range(3):
             scale = max(np.abs(sp[:, q]).max(), 1e-300)
-            assert np.abs(gsp[:, q] - sp[:, q]).max() <= (1e-7 if kerr else 1e-11) * scale + 1e-14, q
+            assert np.abs(gsp[:, q] - sp[:, q]).max() <= (1e-9 if kerr else 1e-11) * scale + 1e-14, q
 
 
 @pytest.mark.parametrize("name", list(CASES))
