@@ -478,8 +478,10 @@ def cpu_leg(W, wl, forms, checks, variant_checks):
         vwl = W.workload(vname)
         verrors[vname] = {}
         for name, (vdt, states) in vchecks.items():
+            vbox = kerr_box(vwl) if vwl.get("metric") == "mks" else None
             verrors[vname][name] = {
-                f"step_{s}": oracle_step_checked(O, vwl, Pin, vdt, threads, Pgpu=Pout)[2] for s, Pin, Pout in states}
+                f"step_{s}": oracle_step_checked(O, vwl, Pin, vdt, threads, box=vbox, Pgpu=Pout)[2]
+                for s, Pin, Pout in states}
     model = platform.processor()
     try:
         for line in open("/proc/cpuinfo"):
@@ -550,8 +552,9 @@ def main() -> int:
     ap.add_argument("--no-variants", action="store_true", help="only the plain FP64 form of the workload")
     ap.add_argument("--pairs", type=int, default=1_000_000, help="training pairs of the learned guess")
     ap.add_argument("--epochs", type=int, default=8, help="training epochs of the learned guess")
-    ap.add_argument("--variant-workloads", default="emhd2d_modes_256,emhd2d_modes_512",
-                    help="comma-separated other workloads for the four forms")
+    ap.add_argument("--variant-workloads", default="emhd2d_modes_256,emhd2d_modes_512,grmhd3d_kerr_128",
+                    help="comma-separated other workloads for the forms (the ideal-MHD torus runs the FP64, "
+                         "FP32-Jacobian and full-system forms its configuration compares)")
     ap.add_argument("--residual-probe", action="store_true", help="run the residual hook for counters and exit")
     ap.add_argument("--stream", action="store_true", help="run the STREAM probe also with --no-variants")
     args = ap.parse_args()
@@ -621,7 +624,8 @@ def main() -> int:
         for vname in [v for v in args.variant_workloads.split(",") if v and v != args.workload]:
             vwl = W.workload(vname)
             vP0 = W.initial_state(vwl, seed=0)
-            vforms, vchecks = run_forms(grim, W, vwl, vP0, args, FORMS)
+            names = FORMS if vwl["nvar"] == 10 else ["f64", "f32_jacobian", "f64_full_system"]
+            vforms, vchecks = run_forms(grim, W, vwl, vP0, args, names)
             vforms["roofline"] = roofline(vwl, vwl["nvar"], args.steps, vforms["f64"])
             vforms["system_ab"] = {"reduced_over_full": vforms["f64"]["value"] / vforms["f64_full_system"]["value"],
                                    "mean_iters_full": vforms["f64_full_system"]["mean_newton_iters"]}
