@@ -67,6 +67,13 @@ def test_struct_layouts_match_header(lib, tmp_path):
     (dict(chi=0.0), "EMHD"),
     (dict(ls_max=0), "ls_max"),
     (dict(n=[256, 0]), "no zones"),
+    (dict(recon="weno5"), "ng = 3"),
+    (dict(recon="ppm", ng=2), "ng = 3"),
+    (dict(dp_saturation=True), "closure"),
+    (dict(closure=True, phi=0.0), "phi, psi"),
+    (dict(closure=True, dp_saturation=True, sat_width=0.0), "sat_width"),
+    (dict(system="full", riemann="hlle"), "full system"),
+    (dict(ng=3, n=[256, 2]), "n >= ng"),
 ])
 def test_invalid_config_rejected_before_device(lib, mutate, msg):
     wl = W.workload("emhd2d_modes_256")
