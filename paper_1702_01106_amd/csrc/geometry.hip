@@ -119,12 +119,15 @@ __global__ void k_geometry(Layout L, MKS p, double* centre, double* f1, double* 
     }
     double u[4][4], gd, al;
     mks_gcon(p, X1, X2, u, gd, al);
+    // Gamma^l_{m n} = Gamma^l_{n m}: computed for m <= n and stored at both,
+    // so the table is symmetric to the bit
     for (int l = 0; l < 4; ++l)
         for (int m = 0; m < 4; ++m)
-            for (int n = 0; n < 4; ++n) {
+            for (int n = m; n < 4; ++n) {
                 double acc = 0.0;
                 for (int k = 0; k < 4; ++k) acc += u[l][k] * (dg[m][k][n] + dg[n][k][m] - dg[k][m][n]);
                 conn[(size_t)(l * 16 + m * 4 + n) * s + t] = 0.5 * acc;
+                conn[(size_t)(l * 16 + n * 4 + m) * s + t] = 0.5 * acc;
             }
 }
 

@@ -136,8 +136,11 @@ __device__ __forceinline__ void llf_pair(const Phys& ph, const G& g, const Cell&
 // flux of variable v through the face normal to d on the low side of the cell
 // at offset o = (o1, o2, o3) from cell m; PE(v, m, o) is P^E there; Pn(v, m)
 // is P_n of cell m.  SrcGlobal reads the stage buffers; the tiled stage
-// kernel reads its LDS tile and the P_n it loaded ahead.
+// kernel reads its LDS tile and the P_n it loaded ahead.  A source with
+// kNbrX also hands over the EMHD slope points of the zone's six neighbours
+// (emhd_point, nbr_x(d, below, above)) instead of their P^E.
 struct SrcGlobal {
+    static constexpr bool kNbrX = false;
     const StageArgs& a;
     __device__ __forceinline__ long at(long m, int o1, int o2, int o3) const
     {
@@ -332,22 +335,27 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
 #pragma unroll
         for (int d = 0; d < nd; ++d) {
             const double bhd = sE.bh[d + 1], ud = sE.ucon[d + 1];
-            const int e1 = d == 0, e2 = d == 1, e3 = d == 2;
-            double Pm[NV], Pp[NV], Xm[8], Xp[8];
+            double Xm[8], Xp[8];
+            if constexpr (Src::kNbrX) {
+                in.nbr_x(d, Xm, Xp);
+            } else {
+                const int e1 = d == 0, e2 = d == 1, e3 = d == 2;
+                double Pm[NV], Pp[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                Pm[v] = in.PE(v, m, -e1, -e2, -e3);
-                Pp[v] = in.PE(v, m, e1, e2, e3);
+                for (int v = 0; v < NV; ++v) {
+                    Pm[v] = in.PE(v, m, -e1, -e2, -e3);
+                    Pp[v] = in.PE(v, m, e1, e2, e3);
+                }
+                G gm, gp;
+                if constexpr (!G::kFlat) {
+                    const int im = d == 0 ? i - 1 : i, jm = d == 1 ? j - 1 : j;
+                    const int ip = d == 0 ? i + 1 : i, jp = d == 1 ? j + 1 : j;
+                    load_geo(gm, a.geo.centre, (size_t)((long)jm * L.N[0] + im), a.geo.stride);
+                    load_geo(gp, a.geo.centre, (size_t)((long)jp * L.N[0] + ip), a.geo.stride);
+                }
+                emhd_point<NV>(Pm, gm, a.ph, Xm);
+                emhd_point<NV>(Pp, gp, a.ph, Xp);
             }
-            G gm, gp;
-            if constexpr (!G::kFlat) {
-                const int im = d == 0 ? i - 1 : i, jm = d == 1 ? j - 1 : j;
-                const int ip = d == 0 ? i + 1 : i, jp = d == 1 ? j + 1 : j;
-                load_geo(gm, a.geo.centre, (size_t)((long)jm * L.N[0] + im), a.geo.stride);
-                load_geo(gp, a.geo.centre, (size_t)((long)jp * L.N[0] + ip), a.geo.stride);
-            }
-            emhd_point<NV>(Pm, gm, a.ph, Xm);
-            emhd_point<NV>(Pp, gp, a.ph, Xp);
             const double idx = 1.0 / L.dx[d];
             double dX[8];
 #pragma unroll

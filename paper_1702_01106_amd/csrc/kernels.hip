@@ -151,6 +151,158 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) 
     }
 }
 
+// EMHD on the 3-D Kerr grid: the stage right-hand side by columns.  A block
+// takes a tile of kMarchTI x kMarchTJ columns (i, j) (one wave a row) and
+// marches up a chunk of planes k.  The slopes of the EMHD sources need the
+// slope point X (emhd_point) of the zone's six neighbours: the block shares
+// X of each plane through LDS, the waves at the tile's edges computing X of
+// the halo cells (wave 0 row j0-1, wave 3 row j0+4, waves 1 and 2 the columns
+// i0-1 and i0+64), and each lane keeps X of its own column one plane below
+// and above in registers, with the column's metric.  Every cell's X is then
+// derived once a plane (plus one halo cell a wave) instead of six times, and
+// the neighbours' P^E and metrics are never read.  The column's connection
+// (40 distinct Gamma^l_{m n}, the table being symmetric in m, n) is read once
+// a chunk into the lane's own slots of LDS.  Same arithmetic as k_rhs up to
+// the compiler's contraction of products into fused multiply-adds.
+constexpr int kMarchTI = 64, kMarchTJ = 4;
+
+// Slot of Gamma^l_{m n} (q = 16 l + 4 m + n) among the 40 with m <= n.
+__device__ __forceinline__ constexpr int conn_slot(int q)
+{
+    const int l = q / 16, a = (q / 4) % 4, b = q % 4;
+    const int m = a < b ? a : b, n = a < b ? b : a;
+    return l * 10 + m * (7 - m) / 2 + n;
+}
+static_assert(kBlock == kMarchTI * kMarchTJ, "one wave per tile row");
+
+struct SrcMarch {
+    static constexpr bool kNbrX = true;
+    SrcGlobal gl;
+    const GeoKS& g0;      // metric of the zone's column
+    const double* pe;     // P^E of the zone
+    const double* xm;     // X one plane below and above
+    const double* xp;
+    const double (*xl)[kMarchTJ + 2][kMarchTI + 2];  // X of the plane [q][row][col]
+    const double (*cs)[kBlock];                      // connection slots [40][thread]
+    int r, c;             // the zone's row and column in xl
+    __device__ __forceinline__ double F(int d, int v, long m, int o1, int o2, int o3) const
+    {
+        return gl.F(d, v, m, o1, o2, o3);
+    }
+    __device__ __forceinline__ double PE(int v, long m, int o1, int o2, int o3) const
+    {
+        return (o1 | o2 | o3) == 0 ? pe[v] : gl.PE(v, m, o1, o2, o3);
+    }
+    __device__ __forceinline__ double Pn(int v, long m) const { return gl.Pn(v, m); }
+    template <class G>
+    __device__ __forceinline__ void centre(G& g, size_t) const { g = g0; }
+    __device__ __forceinline__ double conn(int q, size_t) const { return cs[conn_slot(q)][threadIdx.x]; }
+    __device__ __forceinline__ void nbr_x(int d, double* Xm, double* Xp) const
+    {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            Xm[q] = d == 0 ? xl[q][r][c - 1] : (d == 1 ? xl[q][r - 1][c] : xm[q]);
+            Xp[q] = d == 0 ? xl[q][r][c + 1] : (d == 1 ? xl[q][r + 1][c] : xp[q]);
+        }
+    }
+};
+
+template <bool X>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_rhs_march(StageArgs a, int kc)
+{
+    constexpr int NV = 10;
+    plain_options<X>(a.ph);
+    __shared__ double xs[2][8][kMarchTJ + 2][kMarchTI + 2];
+    __shared__ double gs[40][kBlock];
+    const Layout& L = a.L;
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int nti = (L.n[0] + kMarchTI - 1) / kMarchTI, ntj = (L.n[1] + kMarchTJ - 1) / kMarchTJ;
+    const int t = blockIdx.x % (nti * ntj), ch = blockIdx.x / (nti * ntj);
+    const int i0 = (t % nti) * kMarchTI, j0 = (t / nti) * kMarchTJ;
+    const int k0 = ch * kc, k1 = min(k0 + kc, L.n[2]);
+    const int i = i0 + lane, j = j0 + w;  // interior indices of the lane's column
+    const bool act = i < L.n[0] && j < L.n[1];
+    // the column's cell and this lane's halo cell (ghost-inclusive), clamped
+    // into the grid where a tile overhangs it; no active zone reads those
+    const int ci = min(i + L.g[0], L.N[0] - 1), cj = min(j + L.g[1], L.N[1] - 1);
+    int hi, hj, hr, hc;
+    bool hon = true;
+    if (w == 0 || w == kMarchTJ - 1) {
+        hi = i;
+        hj = w == 0 ? j0 - 1 : j0 + kMarchTJ;
+        hr = w == 0 ? 0 : kMarchTJ + 1;
+        hc = lane + 1;
+    } else {
+        hi = w == 1 ? i0 - 1 : i0 + kMarchTI;
+        hj = j0 + lane;
+        hr = lane + 1;
+        hc = w == 1 ? 0 : kMarchTI + 1;
+        hon = lane < kMarchTJ;
+    }
+    const int hci = min(max(hi + L.g[0], 0), L.N[0] - 1), hcj = min(max(hj + L.g[1], 0), L.N[1] - 1);
+    GeoKS g0, gh;
+    load_geo(g0, a.geo.centre, (size_t)((long)cj * L.N[0] + ci), a.geo.stride);
+    load_geo(gh, a.geo.centre, (size_t)((long)hcj * L.N[0] + hci), a.geo.stride);
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = m; n < 4; ++n) {
+                const int q = l * 16 + m * 4 + n;
+                gs[conn_slot(q)][threadIdx.x] = a.geo.conn[(size_t)q * a.geo.stride + (size_t)((long)cj * L.N[0] + ci)];
+            }
+    const long C = L.cells;
+    double pe[NV], xm[8], xc[8];
+    {
+        double p0[NV];
+        load_cell<NV>(a.PE, C, L.cell(ci, cj, k0 + L.g[2] - 1), p0);
+        emhd_point<NV>(p0, g0, a.ph, xm);
+    }
+    load_cell<NV>(a.PE, C, L.cell(ci, cj, k0 + L.g[2]), pe);
+    emhd_point<NV>(pe, g0, a.ph, xc);
+    const long nz = L.nz;
+    int buf = 0;
+    for (int kk = k0; kk < k1; ++kk) {
+        const int ck = kk + L.g[2];
+        double pu[NV], xp[8];
+        load_cell<NV>(a.PE, C, L.cell(ci, cj, ck + 1), pu);
+        emhd_point<NV>(pu, g0, a.ph, xp);
+        if (hon) {
+            double ph[NV], xh[8];
+            load_cell<NV>(a.PE, C, L.cell(hci, hcj, ck), ph);
+            emhd_point<NV>(ph, gh, a.ph, xh);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xs[buf][q][hr][hc] = xh[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xs[buf][q][w + 1][lane + 1] = xc[q];
+        __syncthreads();
+        if (act) {
+            const long z = ((long)kk * L.n[1] + j) * L.n[0] + i;
+            double rhs[NV], co[kEmhdCoef];
+            GeoKS g;
+            zone_rhs<NV, GeoKS, 3, true>(a, z, rhs, co, g,
+                                         SrcMarch{SrcGlobal{a}, g0, pe, xm, xp, xs[buf], gs, w + 1, lane + 1});
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.rhs[(long)v * nz + z] = rhs[v];
+#pragma unroll
+            for (int q = 0; q < kEmhdCoef; ++q) a.coef[(long)q * nz + z] = co[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            xm[q] = xc[q];
+            xc[q] = xp[q];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pe[v] = pu[v];
+        buf ^= 1;
+    }
+}
+
+// Planes per block of k_rhs_march.
+constexpr int kMarchPlanes = 8;
+
 // ------------------------------------------------------------------ math hook
 
 __global__ __launch_bounds__(kBlock) void k_math_probe(const double* x, double* out, size_t n)
@@ -323,6 +475,14 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
 template <int NV, class G, bool X>
 hipError_t rhs_x(const StageArgs& a, hipStream_t st)
 {
+    if constexpr (NV == 10 && !G::kFlat && !X) {
+        if (a.L.ndim == 3) {
+            const int nt = ((a.L.n[0] + kMarchTI - 1) / kMarchTI) * ((a.L.n[1] + kMarchTJ - 1) / kMarchTJ);
+            const int nc = (a.L.n[2] + kMarchPlanes - 1) / kMarchPlanes;
+            hipLaunchKernelGGL((k_rhs_march<X>), dim3(nt * nc), dim3(kBlock), 0, st, a, kMarchPlanes);
+            return hipGetLastError();
+        }
+    }
     const bool col = !G::kFlat && a.L.ndim == 3;
     const dim3 grid(col ? nblocks(column_waves(a.L), kBlock / 64) : nblocks(a.L.nz)), blk(kBlock);
     if (a.L.ndim == 1) hipLaunchKernelGGL((k_rhs<NV, G, 1, X>), grid, blk, 0, st, a);

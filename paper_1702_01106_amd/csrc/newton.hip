@@ -618,6 +618,7 @@ struct Tile {
 
 template <int NV, int ND>
 struct SrcTile {
+    static constexpr bool kNbrX = false;
     using T = Tile<ND>;
     const double* pe;  // [NV][PY][PX]
     const double* fx;  // [NV][XY][XX]
