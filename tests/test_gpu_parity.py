@@ -73,8 +73,11 @@ CASES = {
                             gamma=4 / 3, tau_R=1.0, chi=0.01, nu=0.01, name="emhd3d"), None),
     "kerr_ideal": lambda: (W.small("grmhd3d_kerr_128", [28, 24, 6]), None),
     "kerr_emhd": lambda: (W.small("emhd3d_kerr_192", [28, 24, 6]), None),
+    # the column-tiled EMHD Kerr kernel's ragged edges: a second, 6-column
+    # tile in i, a 3-row last tile in j and a 3-plane last chunk in k
+    "kerr_emhd_ragged": lambda: (W.small("emhd3d_kerr_192", [70, 23, 11]), None),
 }
-KERR = ("kerr_ideal", "kerr_emhd")
+KERR = ("kerr_ideal", "kerr_emhd", "kerr_emhd_ragged")
 
 
 def _state(name, wl):
