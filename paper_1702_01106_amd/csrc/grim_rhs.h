@@ -295,6 +295,18 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
         trow<NV, 2>(PE, sE, T[2]);
         trow<NV, 3>(PE, sE, T[3]);
         double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        // ga and gb as sums over l of u_l times Gamma^l contracted with the
+        // tensors wa^{n mu} = u^n bhat^mu and wb^{mu n} = bhat^mu bhat^n
+        double wa[4][4], wb[4][4];
+        if constexpr (NV == 10) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    wa[a][b] = sE.ucon[a] * sE.bh[b];
+                    wb[a][b] = sE.bh[a] * sE.bh[b];
+                }
+        }
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             double c[4][4];  // Gamma^l_{a b}
@@ -305,13 +317,16 @@ __device__ __forceinline__ void zone_rhs(const StageArgs& a, long z, double* rhs
 #pragma unroll
                 for (int kap = 0; kap < 4; ++kap) s4[n] += T[kap][l] * c[n][kap];
             if constexpr (NV == 10) {
+                double ta = 0.0, tb = 0.0;
 #pragma unroll
-                for (int mu = 0; mu < 4; ++mu)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) {
-                        ga += sE.bh[mu] * c[n][mu] * sE.ucon[n] * sE.ucov[l];
-                        gb += sE.bh[mu] * sE.bh[n] * c[mu][n] * sE.ucov[l];
+                    for (int b = 0; b < 4; ++b) {
+                        ta = fma(c[a][b], wa[a][b], ta);
+                        tb = fma(c[a][b], wb[a][b], tb);
                     }
+                ga = fma(ta, sE.ucov[l], ga);
+                gb = fma(tb, sE.ucov[l], gb);
 #pragma unroll
                 for (int n = 0; n < 4; ++n) gdv += c[l][n] * sE.ucon[n];
             }
