@@ -566,6 +566,28 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
 // work-queue variant, where a lane that finished took the next zone of its
 // wave's range, ran 20-45% slower on every workload measured and was
 // dropped.)
+// Zones of a 3-D grid in bricks of kBrickI x kBrickJ x kBrickK, one brick a
+// wave: a wave runs as long as its slowest zone, and the zones that need an
+// extra Newton iteration come in clusters, which a compact brick meets with
+// fewer waves than a row of 64.
+constexpr int kBrickI = 8, kBrickJ = 4, kBrickK = 2;
+static_assert(kBrickI * kBrickJ * kBrickK == kWave, "a brick per wave");
+inline long brick_count(const Layout& L)
+{
+    return (long)((L.n[0] + kBrickI - 1) / kBrickI) * ((L.n[1] + kBrickJ - 1) / kBrickJ) *
+           ((L.n[2] + kBrickK - 1) / kBrickK);
+}
+__device__ __forceinline__ bool brick_zone(const Layout& L, unsigned b, unsigned lane, long& z)
+{
+    const unsigned nbi = ((unsigned)L.n[0] + kBrickI - 1) / kBrickI, nbj = ((unsigned)L.n[1] + kBrickJ - 1) / kBrickJ;
+    const unsigned r = b / nbi, bk = r / nbj;
+    const unsigned i = (b - r * nbi) * kBrickI + lane % kBrickI;
+    const unsigned j = (r - bk * nbj) * kBrickJ + (lane / kBrickI) % kBrickJ;
+    const unsigned k = bk * kBrickK + lane / (kBrickI * kBrickJ);
+    z = ((long)k * L.n[1] + j) * L.n[0] + i;
+    return i < (unsigned)L.n[0] && j < (unsigned)L.n[1] && k < (unsigned)L.n[2];
+}
+
 template <int NV, class G, typename JT, int ND, bool FULL, bool X>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
@@ -574,8 +596,15 @@ __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
     // 4-6% slower on the Kerr tori)
     // (the column order of the Kerr rhs kernel, with or without the XCD
     // renumbering, made this one 7% slower on the 192x192x96 torus)
-    const long z = (long)xcd_block(blockIdx.x, gridDim.x) * kWave + threadIdx.x;
-    bool active = z < a.s.L.nz;
+    const unsigned wb = xcd_block(blockIdx.x, gridDim.x);
+    long z;
+    bool active;
+    if (ND == 0 && a.s.L.ndim == 3) {
+        active = brick_zone(a.s.L, wb, threadIdx.x, z);
+    } else {
+        z = (long)wb * kWave + threadIdx.x;
+        active = z < a.s.L.nz;
+    }
     const bool retry = a.pass == 2;
     if (retry) {
         active = active && (a.flags[z] & kFlagRetry);
@@ -844,7 +873,8 @@ hipError_t stage_tiled(const NewtonArgs& a, int jac_f32, hipStream_t st)
 template <int NV, class G, int ND, bool FULL, bool X>
 hipError_t newton_nd(const NewtonArgs& a, int jac_f32, hipStream_t st)
 {
-    const dim3 grid((unsigned)((a.s.L.nz + kWave - 1) / kWave)), blk(kWave);
+    const long waves = ND == 0 && a.s.L.ndim == 3 ? brick_count(a.s.L) : (a.s.L.nz + kWave - 1) / kWave;
+    const dim3 grid((unsigned)waves), blk(kWave);
     NewtonArgs b = a;
     if (jac_f32) {
         // FP32 pass, then the FP64 retry of the zones it marks (needs flags)
