@@ -123,6 +123,29 @@ __global__ __launch_bounds__(kBlock) void k_fluxes(StageArgs a, FaceRanges r)
     else face_flux<NV, G, 3, X>(a, i, j, k);
 }
 
+// The faces of a 3-D Kerr grid by cells: a thread takes the low x-, y- and
+// z-faces of one cell of the box one cell wider each side than the
+// interior, as flux-CT needs.  The x- and y-faces are computed for every
+// cell of the box (those at the box's low i and j edge are faces no kernel
+// reads; their stencils stay inside the array), so both are one basic block;
+// a block is one plane, and the z-face waits for the planes above the first.
+// EMHD on the 192x192x96 torus: 1.22 -> 1.14 ms a step against k_fluxes.
+template <int NV, class G, bool X>
+__global__ __launch_bounds__(kBlock) void k_fluxes_cell(StageArgs a)
+{
+    plain_options<X>(a.ph);
+    const Layout& L = a.L;
+    const unsigned c0 = L.n[0] + 2, c1 = L.n[1] + 2, c2 = L.n[2] + 2;
+    const unsigned b = blockIdx.x, kk = b % c2;
+    const unsigned t = (b / c2) * kBlock + threadIdx.x;
+    if (t >= c0 * c1) return;
+    const unsigned q = t / c0;
+    const int i = L.g[0] - 1 + (int)(t - q * c0), j = L.g[1] - 1 + (int)q, k = L.g[2] - 1 + (int)kk;
+    face_flux<NV, G, 1, X>(a, i, j, k);
+    face_flux<NV, G, 2, X>(a, i, j, k);
+    if (k >= L.g[2]) face_flux<NV, G, 3, X>(a, i, j, k);
+}
+
 // One thread per interior zone: the stage right-hand side (zone_rhs), stored
 // for the Newton kernel.
 template <int NV, class G, int ND, bool X>
@@ -525,6 +548,15 @@ hipError_t fluxes_t(const StageArgs& a, hipStream_t st)
     }
     r.first[3] = blocks;
     for (int d = nd; d < 3; ++d) r.first[d] = blocks;
+    if constexpr (!G::kFlat && NV == 10) {
+        // (ideal MHD: 5% slower than the plane-interleaved faces with the XCD
+        // renumbering on the 128x128x64 torus)
+        if (nd == 3 && !uses_options(a.ph)) {
+            const unsigned cb = plane_blocks((long)(L.n[0] + 2) * (L.n[1] + 2), L.n[2] + 2, kBlock);
+            hipLaunchKernelGGL((k_fluxes_cell<NV, G, false>), dim3(cb), dim3(kBlock), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     if (uses_options(a.ph)) hipLaunchKernelGGL((k_fluxes<NV, G, true>), dim3(blocks), dim3(kBlock), 0, st, a, r);
     else hipLaunchKernelGGL((k_fluxes<NV, G, false>), dim3(blocks), dim3(kBlock), 0, st, a, r);
     return hipGetLastError();
