@@ -207,6 +207,7 @@ def check_steps(wl, steps):
 # within 15 degrees of the equator) with a halo of 2 Ng = 4 zones; X3 is
 # periodic, so the box wraps in k.
 BOX_N, BOX_HALO = 32, 4
+CPU_SAMPLE_S = 10.0  # oracle time the cpu_baseline sample runs for
 
 
 def kerr_box(wl):
@@ -385,6 +386,37 @@ def oracle_step_checked(O, wl, Pin, dt, threads, box=None, Pgpu=None):
     return ref, info, compare_stage(o2, wl2, Pn2, PEg2, dt, Pgpu, ref, rr)
 
 
+def oracle_throughput(O, wl, states, dt, threads, box, min_seconds=CPU_SAMPLE_S, max_steps=400):
+    """Oracle step-time over the states (box with halo, or whole grid),
+    cycling through them until min_seconds of oracle time have passed (or
+    max_steps steps): (zone-updates, seconds, steps)."""
+    g = BOX_HALO // 2
+    if box is not None:
+        big = (box[0] - g, box[1] - g, box[2] - g)
+        o1 = O.Oracle(dict(box_workload(wl, big, BOX_N + 2 * g), nthreads=threads))
+        o2 = O.Oracle(dict(box_workload(wl, box, BOX_N), nthreads=threads))
+    else:
+        o1 = o2 = O.Oracle(dict(wl, nthreads=threads))
+    t_all, zu, steps = 0.0, 0, 0
+    while t_all < min_seconds and steps < max_steps:
+        for Pin in states:
+            if box is not None:
+                Pn1 = np.ascontiguousarray(Pin[:, g:-g, g:-g, g:-g])
+                Pn2 = np.ascontiguousarray(Pin[:, 2 * g:-2 * g, 2 * g:-2 * g, 2 * g:-2 * g])
+                PEg1 = Pin
+            else:
+                Pn1 = Pn2 = Pin
+                PEg1 = o1.fill_ghosts(Pin)
+            t0 = time.perf_counter()
+            Ph, _, _, _, _ = o1.stage_ghosted(Pn1, PEg1, 0.5 * dt)
+            PEg2 = Ph if box is not None else o2.fill_ghosts(Ph)
+            o2.stage_ghosted(Pn2, PEg2, dt)
+            t_all += time.perf_counter() - t0
+            zu += Pn2[0].size
+            steps += 1
+    return zu, t_all, steps
+
+
 def compare_stage(o, wl, Pn, PEg, dtp, Pgpu, ref, rr):
     """Per-primitive comparison of the GPU's stage answer Pgpu with the
     oracle's ref (final norms rr) for a stage with P_n, ghost-filled P^E and
@@ -452,27 +484,27 @@ def cpu_leg(W, wl, forms, checks, variant_checks):
     kerr = wl.get("metric") == "mks"
     box = kerr_box(wl) if kerr else None
     errors = {}
-    t_all, zone_updates = 0.0, 0
     for name, states in checks.items():
         errs = {}
         for s, Pin, Pout in states:
             _, info, rep = oracle_step_checked(O, wl, Pin, forms[name]["dt"], threads, box=box, Pgpu=Pout)
             log(f"oracle check {name} step {s}: within {rep['within']}")
-            if name == "f64":
-                t_all += info["oracle_seconds"]
-                zone_updates += Pout[0].size
             errs[f"step_{s}"] = dict(rep, oracle=info)
         errors[name] = errs
+    zone_updates, t_all, nsteps = oracle_throughput(O, wl, [x[1] for x in checks["f64"]], forms["f64"]["dt"],
+                                                    threads, box)
+    log(f"oracle throughput: {nsteps} steps in {t_all:.1f} s")
     one_core = None
     if kerr:
         s, Pin, _ = checks["f64"][0]
         _, info, _ = oracle_step_checked(O, wl, Pin, forms["f64"]["dt"], 1, box=box)
         one_core = BOX_N ** 3 / info["oracle_seconds"]
-        sample = (f"one step of a {BOX_N}^3 subdomain in the torus body with a {BOX_HALO}-zone halo, from the "
-                  f"GPU's states before steps {[x[0] for x in checks['f64']]}; stage 1 runs on the "
-                  f"{BOX_N + BOX_HALO}^3 box around it, counted as {BOX_N}^3 zone-updates")
+        sample = (f"{nsteps} steps, each one step of a {BOX_N}^3 subdomain in the torus body with a "
+                  f"{BOX_HALO}-zone halo from one of the GPU's states before steps {[x[0] for x in checks['f64']]} "
+                  f"in turn; stage 1 runs on the {BOX_N + BOX_HALO}^3 box around it, counted as {BOX_N}^3 "
+                  f"zone-updates")
     else:
-        sample = "the last step of the workload on the full grid, from the GPU's state before it"
+        sample = f"{nsteps} repetitions of the last step of the workload on the full grid, from the GPU's state before it"
     verrors = {}
     for vname, vchecks in variant_checks.items():
         vwl = W.workload(vname)
