@@ -3,7 +3,7 @@
 //
 //   R(P) FP64 always (a8).  Jacobian by forward differences with the
 //   perturbation rule of Sec. 3.1 (a9): column j = (R(P_eps,j) - R(P))/h_j,
-//   h_j = P_eps,j - P_j.  Dense LU with partial pivoting (a10): row swaps are
+//   h_j = P_eps,j - P_j.  Dense LU with threshold partial pivoting (a10): row swaps are
 //   branch-free selects so J never leaves registers.  Quadratic backtracking
 //   line search (a11, Sec. 3.2): each new lambda is the minimiser of the
 //   quadratic model, or with the safeguard option that minimiser kept in
@@ -156,7 +156,7 @@ __device__ __forceinline__ void Pc_from_net(const double* pn, const float* y, do
 
 // The Newton direction dP (zero in the B entries) at P, whose residual is R:
 // the finite-difference Jacobian over the system's unknowns, column by
-// column, then LU with partial pivoting.  The energy row of the linear
+// column, then LU with threshold partial pivoting.  The energy row of the linear
 // system is taken as energy + mass (both sides), which removes the rest-mass
 // energy from it: an elementary row operation, so dP is unchanged, but the
 // mass row's rho entry (u^0) no longer competes with the energy row's
