@@ -388,8 +388,9 @@ def oracle_step_checked(O, wl, Pin, dt, threads, box=None, Pgpu=None):
 
 def oracle_throughput(O, wl, states, dt, threads, box, min_seconds=CPU_SAMPLE_S, max_steps=400):
     """Oracle step-time over the states (box with halo, or whole grid),
-    cycling through them until min_seconds of oracle time have passed (or
-    max_steps steps): (zone-updates, seconds, steps)."""
+    cycling through them, one pass at least, until min_seconds of oracle
+    time have passed or max_steps steps have run: (zone-updates, seconds,
+    steps)."""
     g = BOX_HALO // 2
     if box is not None:
         big = (box[0] - g, box[1] - g, box[2] - g)
@@ -397,9 +398,13 @@ def oracle_throughput(O, wl, states, dt, threads, box, min_seconds=CPU_SAMPLE_S,
         o2 = O.Oracle(dict(box_workload(wl, box, BOX_N), nthreads=threads))
     else:
         o1 = o2 = O.Oracle(dict(wl, nthreads=threads))
+    if not states or max_steps < 1:
+        raise ValueError("oracle_throughput needs a state and a step")
     t_all, zu, steps = 0.0, 0, 0
-    while t_all < min_seconds and steps < max_steps:
+    while steps == 0 or (t_all < min_seconds and steps < max_steps):
         for Pin in states:
+            if steps >= max_steps:
+                break
             if box is not None:
                 Pn1 = np.ascontiguousarray(Pin[:, g:-g, g:-g, g:-g])
                 Pn2 = np.ascontiguousarray(Pin[:, 2 * g:-2 * g, 2 * g:-2 * g, 2 * g:-2 * g])

@@ -1,0 +1,42 @@
+"""CPU checks of the benchmark's host logic: the one-GPU guard and the
+cpu_baseline sample (the oracle's step time, cycled over the given states
+until the requested oracle time has passed or the step cap is reached)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_1702_01106_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_oracle_throughput_counts_box_steps(oracle_mod):
+    wl = W.workload("emhd3d_kerr_192")
+    P0 = W.initial_state(wl, seed=0)
+    box = bench.kerr_box(wl)
+    Pin = bench.cut(P0, box, True)
+    dt = 1e-3
+    # a zero time budget still runs one pass over the states
+    zu, t, n = bench.oracle_throughput(oracle_mod, wl, [Pin, Pin], dt, 2, box, min_seconds=0.0)
+    assert n == 2 and zu == 2 * bench.BOX_N ** 3 and t > 0.0
+    # the step cap bounds the sample
+    zu, t, n = bench.oracle_throughput(oracle_mod, wl, [Pin], dt, 2, box, min_seconds=1e9, max_steps=3)
+    assert n == 3 and zu == 3 * bench.BOX_N ** 3
+
+
+def test_oracle_throughput_whole_grid(oracle_mod):
+    wl = W.small("emhd2d_modes_256", [32, 16])
+    P0 = np.ascontiguousarray(W.initial_state(wl, seed=0))
+    zu, t, n = bench.oracle_throughput(oracle_mod, wl, [P0], 1e-3, 2, None, min_seconds=0.0)
+    assert n == 1 and zu == 32 * 16 and t > 0.0
