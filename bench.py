@@ -321,6 +321,57 @@ def roofline(wl, nvar, steps, form):
     }
 
 
+# bytes a zone-stage must move through each kernel of the three-kernel path
+# (faces, stored right-hand side, Newton), the interior counted once and the
+# 2-D metric tables, shared by every plane, left out: faces read P^E and
+# write a face per direction; the right-hand side reads the three faces, P^E
+# and P_n and writes rhs and (EMHD) the 13-double bundle; the Newton kernel
+# reads rhs, the bundle and P_n and writes P
+def kernel_alg_bytes(nvar):
+    w = 8 * nvar
+    bundle = 8 * 13 if nvar == 10 else 0
+    return {"face_flux": w + 3 * w, "stage_rhs": 5 * w + w + bundle, "newton": w + bundle + w + w}
+
+
+def measured_traffic(workload):
+    """Measured HBM bytes per launch of each kernel group from the committed
+    counters, if they were taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return {}
+    if d.get("source_sha256_16") != kernel_source_hash():
+        return {}
+    out = {}
+    for name, (rd, wr) in d.get("read_write_bytes", {}).items():
+        for group, key in (("face_flux", "k_fluxes"), ("stage_rhs", "k_rhs"), ("newton", "k_newton<")):
+            if key in name:
+                out[group] = rd + wr
+    return out
+
+
+def kernel_table(wl, nvar, steps, form):
+    """Per kernel group of the three-kernel path: time per step, the
+    algorithmic bytes per step and their rate against the HBM peak, and the
+    measured bytes per launch where counters exist (None otherwise)."""
+    kms = form["kernel_ms_per_step"]
+    if "face_flux" not in kms:
+        return None
+    zones = int(np.prod(wl["n"]))
+    alg = kernel_alg_bytes(nvar)
+    meas = measured_traffic(wl["name"])
+    table = {}
+    for group in ("face_flux", "stage_rhs", "newton"):
+        if group not in kms:
+            continue
+        b = alg[group] * zones * 2  # two stages a step
+        gbs = b / (kms[group] * 1e-3) / 1e9
+        table[group] = {"ms_per_step": kms[group], "alg_bytes_per_step": b, "alg_GBps": gbs,
+                        "hbm_frac": gbs / HBM_PEAK_GBS, "measured_bytes_per_launch": meas.get(group)}
+    return table
+
+
 # ------------------------------------------------------------------ CPU leg
 
 FAMILY = [[0], [1], [2, 3, 4], [5, 6, 7], [8], [9]]
@@ -642,6 +693,7 @@ def main() -> int:
         "n_fail": head["n_fail"],
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "roofline": roofline(wl, nvar, args.steps, head),
+        "kernels": kernel_table(wl, nvar, args.steps, head),
         "forms": {k: v for k, v in forms.items() if k != "f64"},
     }
     if "f64_full_system" in forms:

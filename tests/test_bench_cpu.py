@@ -40,3 +40,16 @@ def test_oracle_throughput_whole_grid(oracle_mod):
     P0 = np.ascontiguousarray(W.initial_state(wl, seed=0))
     zu, t, n = bench.oracle_throughput(oracle_mod, wl, [P0], 1e-3, 2, None, min_seconds=0.0)
     assert n == 1 and zu == 32 * 16 and t > 0.0
+
+
+def test_kernel_table_bytes():
+    wl = W.workload("emhd3d_kerr_192")
+    zones = 192 * 192 * 96
+    t = bench.kernel_table(wl, 10, 20, {"kernel_ms_per_step": {"face_flux": 1.0, "stage_rhs": 1.0, "newton": 1.0}})
+    # per zone-stage: faces 10 + 30 doubles, rhs 50 read + 10 + 13 written, Newton 10 + 13 + 10 read + 10 written
+    assert t["face_flux"]["alg_bytes_per_step"] == 2 * zones * 8 * 40
+    assert t["stage_rhs"]["alg_bytes_per_step"] == 2 * zones * 8 * 73
+    assert t["newton"]["alg_bytes_per_step"] == 2 * zones * 8 * 43
+    assert abs(t["newton"]["hbm_frac"] - 2 * zones * 8 * 43 / 1e-3 / 8e12) < 1e-12
+    # the one-kernel stage has no split to report
+    assert bench.kernel_table(W.workload("emhd2d_modes_256"), 10, 20, {"kernel_ms_per_step": {"newton": 1.0}}) is None
