@@ -60,6 +60,17 @@ def _floored(wl, P):
     return fl.ravel()
 
 
+def _kerr_piece(name, n):
+    """The named torus workload on n zones of its own zone size, starting at
+    r = 6.5 and just above the equator."""
+    wl = W.workload(name)
+    dx = [(wl["x_end"][d] - wl["x_start"][d]) / wl["n"][d] for d in range(3)]
+    i0 = int(round((np.log(6.5) - wl["x_start"][0]) / dx[0]))
+    j0 = wl["n"][1] // 2 - 1
+    xs = [wl["x_start"][0] + i0 * dx[0], wl["x_start"][1] + j0 * dx[1], wl["x_start"][2]]
+    return dict(wl, n=list(n), x_start=xs, x_end=[xs[d] + n[d] * dx[d] for d in range(3)])
+
+
 CASES = {
     # name: (workload dict, initial state)
     "srmhd1d": lambda: (W.workload("srmhd1d_alfven_128"), None),
@@ -76,8 +87,13 @@ CASES = {
     # the column-tiled EMHD Kerr kernel's ragged edges: a second, 6-column
     # tile in i, a 3-row last tile in j and a 3-plane last chunk in k
     "kerr_emhd_ragged": lambda: (W.small("emhd3d_kerr_192", [70, 23, 11]), None),
+    # smaller than one column tile, one Newton brick and one plane chunk in
+    # every direction: a 9x3x5 piece of the torus body at the full grid's
+    # zone size
+    "kerr_emhd_tiny": lambda: (_kerr_piece("emhd3d_kerr_192", [9, 3, 5]), None),
+    "kerr_ideal_tiny": lambda: (_kerr_piece("grmhd3d_kerr_128", [9, 3, 5]), None),
 }
-KERR = ("kerr_ideal", "kerr_emhd", "kerr_emhd_ragged")
+KERR = ("kerr_ideal", "kerr_emhd", "kerr_emhd_ragged", "kerr_emhd_tiny", "kerr_ideal_tiny")
 
 
 def _state(name, wl):
