@@ -199,6 +199,38 @@ def check_states(grim, wl, P0, dt, steps, weights=None, box=None):
     return out
 
 
+def final_state(grim, wl, P0, dt, steps):
+    """The GPU's state after `steps` graph-replayed steps from P0."""
+    ctx = grim.Context(wl)
+    ctx.set_prims(P0)
+    ctx.run(dt, steps, use_graph=True, want_stats=False)
+    P = ctx.get_prims()
+    ctx.close()
+    return P
+
+
+# a full-grid oracle run of the whole workload fits the CPU leg's time up to
+# about this many zones (the ideal-MHD torus, 1.05M zones, takes ~10-20 s)
+E2E_MAX_ZONES = 1_100_000
+
+
+def end_to_end(O, wl, P0, dt, steps, Pgpu, threads):
+    """The oracle's full-grid run of the workload from P0 against the GPU's
+    state after the same steps: per primitive, the largest difference over
+    max |P_v| of the oracle's state.  Reported, not bounded: after several
+    steps the two runs also differ by the tolerance each Newton solve leaves
+    open, carried forward."""
+    o = O.Oracle(dict(wl, nthreads=threads))
+    t0 = time.perf_counter()
+    ref, _ = o.step(P0, dt, steps)
+    seconds = time.perf_counter() - t0
+    nv = wl["nvar"]
+    rel = {PRIM_NAMES[v] if nv == 10 or v < 8 else str(v):
+           float(np.abs(Pgpu[v] - ref[v]).max() / max(np.abs(ref[v]).max(), 1e-300)) for v in range(nv)}
+    return {"steps": steps, "zones": int(ref[0].size), "oracle_seconds": seconds, "threads": threads,
+            "max_rel_diff": rel}
+
+
 def check_steps(wl, steps):
     return sorted({1, max(1, steps // 2), steps}) if wl.get("metric") == "mks" else [steps]
 
@@ -527,7 +559,7 @@ def floored_zones(wl, P):
     return ((np.abs(P[0] - rf) <= 1e-12 * rf) | (np.abs(P[1] - uf) <= 1e-12 * uf)).ravel()
 
 
-def cpu_leg(W, wl, forms, checks, variant_checks):
+def cpu_leg(W, wl, forms, checks, variant_checks, variant_final=None):
     """The oracle (test infrastructure, plain C) on the host: its throughput
     on a bounded sample of the workload, and the per-primitive error of every
     GPU form against it on the same inputs."""
@@ -570,6 +602,10 @@ def cpu_leg(W, wl, forms, checks, variant_checks):
             verrors[vname][name] = {
                 f"step_{s}": oracle_step_checked(O, vwl, Pin, vdt, threads, box=vbox, Pgpu=Pout)[2]
                 for s, Pin, Pout in states}
+    e2e = {}
+    for vname, (vP0, vdt, vsteps, Pf) in (variant_final or {}).items():
+        e2e[vname] = end_to_end(O, W.workload(vname), vP0, vdt, vsteps, Pf, threads)
+        log(f"oracle end-to-end {vname}: {e2e[vname]['oracle_seconds']:.1f} s")
     model = platform.processor()
     try:
         for line in open("/proc/cpuinfo"):
@@ -589,7 +625,7 @@ def cpu_leg(W, wl, forms, checks, variant_checks):
     }
     if one_core is not None:
         base["value_one_core"] = one_core
-    return base, errors, verrors
+    return base, errors, verrors, e2e
 
 
 # ------------------------------------------------------------------ probes
@@ -705,7 +741,7 @@ def main() -> int:
             "newton_ms_per_step_reduced": head["kernel_ms_per_step"].get("newton"),
             "newton_ms_per_step_full": full["kernel_ms_per_step"].get("newton"),
         }
-    variant_checks = {}
+    variant_checks, variant_final = {}, {}
     if args.stream or not args.no_variants:
         out["stream"] = stream_probe(grim, wl)
     if not args.no_variants:
@@ -720,13 +756,19 @@ def main() -> int:
                                    "mean_iters_full": vforms["f64_full_system"]["mean_newton_iters"]}
             variants[vname] = vforms
             variant_checks[vname] = {k: (vforms[k]["dt"], v) for k, v in vchecks.items()}
+            if vwl.get("metric") == "mks" and vP0[0].size <= E2E_MAX_ZONES and not args.no_cpu_baseline:
+                vdt = vforms["f64"]["dt"]
+                variant_final[vname] = (vP0, vdt, args.steps, final_state(grim, dict(vwl, jac="f64"), vP0, vdt,
+                                                                          args.steps))
         out["variants"] = variants
     if not args.no_cpu_baseline:
-        base, errors, verrors = cpu_leg(W, wl, forms, checks, variant_checks)
+        base, errors, verrors, e2e = cpu_leg(W, wl, forms, checks, variant_checks, variant_final)
         out["cpu_baseline"] = base
         out["error_vs_oracle"] = errors
         for vname, e in verrors.items():
             out["variants"][vname]["error_vs_oracle"] = e
+        for vname, e in e2e.items():
+            out["variants"][vname]["end_to_end_vs_oracle"] = e
         out["gpu_over_cpu"] = value / base["value"]
     print(json.dumps(out), flush=True)
     return 0

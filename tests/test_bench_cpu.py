@@ -53,3 +53,19 @@ def test_kernel_table_bytes():
     assert abs(t["newton"]["hbm_frac"] - 2 * zones * 8 * 43 / 1e-3 / 8e12) < 1e-12
     # the one-kernel stage has no split to report
     assert bench.kernel_table(W.workload("emhd2d_modes_256"), 10, 20, {"kernel_ms_per_step": {"newton": 1.0}}) is None
+
+
+def test_end_to_end_reports_per_primitive(oracle_mod):
+    wl = W.small("grmhd3d_kerr_128", [16, 16, 8])
+    P0 = W.initial_state(wl, seed=0)
+    o = oracle_mod.Oracle(dict(wl, nthreads=2))
+    dt = o.cfl_dt(P0, wl["cfl"])
+    ref, _ = o.step(P0, dt, 2)
+    r = bench.end_to_end(oracle_mod, wl, P0, dt, 2, ref, 2)
+    assert r["steps"] == 2 and r["zones"] == 16 * 16 * 8
+    assert set(r["max_rel_diff"]) == set(bench.PRIM_NAMES[:8])
+    assert all(v == 0.0 for v in r["max_rel_diff"].values())
+    bad = ref.copy()
+    bad[1, 3, 4, 5] *= 1.0 + 1e-3
+    r2 = bench.end_to_end(oracle_mod, wl, P0, dt, 2, bad, 2)
+    assert r2["max_rel_diff"]["u"] > 0.0 and r2["max_rel_diff"]["rho"] == 0.0
