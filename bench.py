@@ -405,6 +405,31 @@ def kernel_table(wl, nvar, steps, form):
     return table
 
 
+def step_roofline(wl, nvar, steps, form, roof):
+    """The step's roofline over the three-kernel path: each kernel's lower
+    bound is the larger of its algorithmic bytes at the HBM peak and its
+    algorithmic flops at the FP64 peak (faces and right-hand side counted
+    with the Minkowski operation counts, so a lower bound in Kerr; the Newton
+    kernel with its counted flops), summed over the kernels of a step and
+    divided by their measured time."""
+    table = kernel_table(wl, nvar, steps, form)
+    if table is None:
+        return None
+    zones = int(np.prod(wl["n"]))
+    alg = kernel_alg_bytes(nvar)
+    flops = {"face_flux": wl["ndim"] * zones * FACE_FLOPS[nvar], "stage_rhs": zones * RHS_FLOPS_2D[nvar],
+             "newton": roof["flops_per_launch"]}
+    per = {}
+    for group in ("face_flux", "stage_rhs", "newton"):
+        tb = alg[group] * zones / (HBM_PEAK_GBS * 1e9)
+        tf = flops[group] / (FP64_PEAK_TFLOPS * 1e12)
+        per[group] = {"bound": "hbm" if tb >= tf else "alu", "t_roofline_ms_per_launch": max(tb, tf) * 1e3}
+    t_roof = 2 * sum(v["t_roofline_ms_per_launch"] for v in per.values())
+    t_meas = sum(table[g]["ms_per_step"] for g in per)
+    return {"t_roofline_ms_per_step": t_roof, "t_measured_ms_per_step": t_meas, "frac": t_roof / t_meas,
+            "per_kernel": per}
+
+
 # ------------------------------------------------------------------ CPU leg
 
 FAMILY = [[0], [1], [2, 3, 4], [5, 6, 7], [8], [9]]
@@ -736,6 +761,7 @@ def main() -> int:
         "kernel_ms_per_step": head["kernel_ms_per_step"],
         "roofline": roofline(wl, nvar, args.steps, head),
         "kernels": kernel_table(wl, nvar, args.steps, head),
+        "step_roofline": step_roofline(wl, nvar, args.steps, head, roofline(wl, nvar, args.steps, head)),
         "forms": {k: v for k, v in forms.items() if k != "f64"},
     }
     if "f64_full_system" in forms:

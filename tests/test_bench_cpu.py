@@ -69,3 +69,16 @@ def test_end_to_end_reports_per_primitive(oracle_mod):
     bad[1, 3, 4, 5] *= 1.0 + 1e-3
     r2 = bench.end_to_end(oracle_mod, wl, P0, dt, 2, bad, 2)
     assert r2["max_rel_diff"]["u"] > 0.0 and r2["max_rel_diff"]["rho"] == 0.0
+
+
+def test_step_roofline_sums_kernel_bounds():
+    wl = W.workload("emhd3d_kerr_192")
+    zones = 192 * 192 * 96
+    form = {"kernel_ms_per_step": {"face_flux": 1.0, "stage_rhs": 1.0, "newton": 2.0}}
+    r = bench.step_roofline(wl, 10, 20, form, {"flops_per_launch": 15.0e9})
+    faces = zones * 8 * 40 / 8e12 * 1e3          # HBM bound: 400 B a zone-stage
+    rhs = zones * 8 * 73 / 8e12 * 1e3
+    newton = max(zones * 8 * 43 / 8e12, 15.0e9 / 78.6e12) * 1e3
+    assert abs(r["t_roofline_ms_per_step"] - 2 * (faces + rhs + newton)) < 1e-12
+    assert r["per_kernel"]["newton"]["bound"] == "alu" and r["per_kernel"]["stage_rhs"]["bound"] == "hbm"
+    assert abs(r["frac"] - r["t_roofline_ms_per_step"] / 4.0) < 1e-12
