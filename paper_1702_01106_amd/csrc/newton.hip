@@ -561,11 +561,6 @@ __device__ __forceinline__ void flush_stats(const NewtonArgs& a, const LaneStats
     }
 }
 
-// A zone per lane: the wave runs until its slowest zone has finished.  ND > 0:
-// fused with the stage right-hand side of an ND-dimensional grid.  (A
-// work-queue variant, where a lane that finished took the next zone of its
-// wave's range, ran 20-45% slower on every workload measured and was
-// dropped.)
 // Zones of a 3-D grid in bricks of kBrickI x kBrickJ x kBrickK, one brick a
 // wave: a wave runs as long as its slowest zone, and the zones that need an
 // extra Newton iteration come in clusters, which a compact brick meets with
@@ -588,6 +583,11 @@ __device__ __forceinline__ bool brick_zone(const Layout& L, unsigned b, unsigned
     return i < (unsigned)L.n[0] && j < (unsigned)L.n[1] && k < (unsigned)L.n[2];
 }
 
+// A zone per lane: the wave runs until its slowest zone has finished.  ND > 0:
+// fused with the stage right-hand side of an ND-dimensional grid.  (A
+// work-queue variant, where a lane that finished took the next zone of its
+// wave's range, ran 20-45% slower on every workload measured and was
+// dropped.)
 template <int NV, class G, typename JT, int ND, bool FULL, bool X>
 __global__ __launch_bounds__(kWave) void k_newton(NewtonArgs a)
 {
